@@ -1,0 +1,71 @@
+"""Pins of the oracle's reverse mode (shading NONE) against central finite
+differences of the oracle's forward render, which the other pin files tie
+to the paper.  Loss: L = sum(g * rgba) with a fixed random g."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def _scene(seed, ert=0.0):
+    sc = W.config_small(seed=seed, dims=(7, 6, 8), dtype=np.float32, image=(9, 8),
+                        shading="none", ert=ert)
+    return sc
+
+
+def _loss(orc, vol_arr, sc, tf, g):
+    v = orc.Volume(vol_arr, sc.spacing, sc.vmin, sc.vmax)
+    r = orc.render(v, sc.cameras[0], tf, sc.shading, sc.options)
+    return float((r["rgba"] * g).sum())
+
+
+@pytest.mark.parametrize("seed,ert", [(21, 0.0), (22, 0.0), (23, 0.8)])
+def test_grad_tf_matches_fd(orc, seed, ert):
+    """dL/dTF: C is linear in the rgb entries, so their FD is exact up to
+    rounding; the alpha entries are smooth away from ERT decisions."""
+    sc = _scene(seed, ert)
+    rng = np.random.default_rng(seed)
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    g = rng.normal(size=(H, Wd, 4))
+    v = orc.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
+    _, dtf = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, g)
+    tf = sc.tf.astype(np.float64)
+    used = np.argwhere(np.abs(dtf).sum(1) > 0)[:, 0]
+    assert used.size > 5
+    h = 1e-6
+    for i in rng.choice(used, size=min(12, used.size), replace=False):
+        for ch in range(4):
+            tp, tm = tf.copy(), tf.copy()
+            tp[i, ch] += h
+            tm[i, ch] -= h
+            fd = (_loss(orc, sc.volume, sc, tp, g) - _loss(orc, sc.volume, sc, tm, g)) / (2 * h)
+            assert abs(fd - dtf[i, ch]) <= 1e-6 * max(1.0, abs(fd)), (i, ch, fd, dtf[i, ch])
+
+
+@pytest.mark.parametrize("seed", [24, 25])
+def test_grad_volume_matches_fd(orc, seed):
+    sc = _scene(seed)
+    rng = np.random.default_rng(seed)
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    g = rng.normal(size=(H, Wd, 4))
+    vol = sc.volume.astype(np.float64)
+    v = orc.Volume(vol, sc.spacing, sc.vmin, sc.vmax)
+    dvol, _ = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, g)
+    cand = np.argwhere(np.abs(dvol) > 1e-6)
+    assert len(cand) > 10
+    h = 1e-6
+    checked = 0
+    for idx in cand[rng.choice(len(cand), size=min(25, len(cand)), replace=False)]:
+        k, j, i = idx
+        vp, vm = vol.copy(), vol.copy()
+        vp[k, j, i] += h
+        vm[k, j, i] -= h
+        fd = (_loss(orc, vp, sc, sc.tf, g) - _loss(orc, vm, sc, sc.tf, g)) / (2 * h)
+        # a TF breakpoint inside [v-h, v+h] makes the FD one-sided: skip those
+        fd_l = (_loss(orc, vol, sc, sc.tf, g) - _loss(orc, vm, sc, sc.tf, g)) / h
+        fd_r = (_loss(orc, vp, sc, sc.tf, g) - _loss(orc, vol, sc, sc.tf, g)) / h
+        if abs(fd_l - fd_r) > 1e-4 * max(1.0, abs(fd)):
+            continue
+        checked += 1
+        assert abs(fd - dvol[k, j, i]) <= 1e-5 * max(1.0, abs(fd)), (idx, fd, dvol[k, j, i])
+    assert checked >= 10
