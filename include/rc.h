@@ -1,0 +1,196 @@
+/*
+ * rc.h -- C ABI of the MI355X (gfx950) volume raycaster.
+ *
+ * What the library computes follows "Volume Raycasting mit OpenCL"
+ * (Kopal): a voxel grid V: N^3 -> R (Section 2.1, eq. 1) is rendered by
+ * casting one ray per pixel from a camera (Section 3.3, Section 3.10 step
+ * 1), clipping it to a bounding box (Sections 3.3 and 3.6), sampling it at
+ * a regular step with trilinear interpolation (Sections 3.3-3.4, eq. 2),
+ * colouring each sample through a lookup table (Section 3.7), lighting it
+ * with a gradient from the central-difference, Sobel3D or Zucker-Hummel
+ * operator (Sections 3.5 and 3.8, eqs. 3-4, Listing 3), and compositing the
+ * samples with the transparency formula (Section 3.9, eq. 6) until the ray
+ * is opaque.  Empty-space skipping (Section 5.3) uses a grid of 8^3-voxel
+ * bricks with per-brick value ranges.
+ *
+ * Conventions
+ *  - World coordinates: voxel (i,j,k) sits at (i*sx, j*sy, k*sz); the
+ *    volume box is [0,(nx-1)sx] x [0,(ny-1)sy] x [0,(nz-1)sz].
+ *  - Linear voxel arrays are [nz][ny][nx], x fastest.
+ *  - Images are [height][width][4] float32, row 0 at the top, RGBA
+ *    premultiplied over black; a ray that misses the box gives (0,0,0,0).
+ *  - Every device pointer is a HIP device allocation owned by the caller,
+ *    except the bricked copy a volume handle owns.  `stream` is a
+ *    hipStream_t; NULL means the default stream.  All work is enqueued on
+ *    that stream; calls return before it runs.
+ *  - Errors: every argument is checked on the host before anything is
+ *    enqueued, so a failing call leaves no partial work.  A call returns a
+ *    negative rc_status and rc_last_error() describes it.  Nothing aborts
+ *    and nothing throws across this interface.
+ *  - Threading: calls on distinct volumes may run concurrently; one volume
+ *    may be rendered from several threads, but not while it is updated or
+ *    destroyed.
+ */
+#ifndef RC_H
+#define RC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RC_OK = 0,
+    RC_E_INVALID = -1,      /* a bad argument (null pointer, size, enum, NaN ...) */
+    RC_E_OOM = -2,          /* a device allocation failed */
+    RC_E_DEVICE = -3,       /* a HIP runtime call failed */
+    RC_E_STATE = -4,        /* wrong call order (e.g. skipping before rc_build_bricks) */
+    RC_E_UNSUPPORTED = -5   /* a valid request this build does not implement */
+} rc_status;
+
+typedef enum { RC_U8 = 0, RC_U16 = 1, RC_F32 = 2 } rc_dtype;
+
+/* Section 3.5: eq. (3), eq. (4), and the Zucker-Hummel operator. */
+typedef enum { RC_GRAD_CENTRAL = 0, RC_GRAD_SOBEL3D = 1, RC_GRAD_ZUCKER_HUMMEL = 2 } rc_gradient_op;
+
+/* Section 3.8.  NONE: colour = TF rgb.  BLINN_PHONG: rgb (ka + kd max(0,N.L))
+ * + ks max(0,N.H)^shininess with the outward normal N = -G/max(|G|,eps).
+ * PAPER_LAMBERT: Listing 3, rgb * dot(normalize(light - p), G/max(|G|,eps)),
+ * unclamped, light a point. */
+typedef enum { RC_SHADE_NONE = 0, RC_SHADE_BLINN_PHONG = 1, RC_SHADE_PAPER_LAMBERT = 2 } rc_shading_model;
+
+typedef enum { RC_ORTHOGRAPHIC = 0, RC_PERSPECTIVE = 1 } rc_projection;
+
+typedef struct rc_volume rc_volume;   /* opaque: owns the bricked device copy */
+
+/* Camera (Section 3.3: one ray per pixel through the image plane).  Look-at
+ * frame f = normalize(target - eye), r = normalize(f x up), u = r x f; pixel
+ * centres at x = 2(px+1/2)/W - 1, y = 1 - 2(py+1/2)/H.  Perspective rays
+ * start at the eye with d = normalize(f + x tan(fov/2) W/H r + y tan(fov/2) u);
+ * orthographic rays have d = f and start at eye + (x W/H r + y u) h/2.
+ * Geometry is double so that ray set-up is exact to FP64. */
+typedef struct {
+    int32_t projection;       /* rc_projection */
+    int32_t width, height;    /* image size in pixels, 1..16384 each */
+    int32_t reserved;         /* must be 0 */
+    double eye[3], target[3], up[3];
+    double fov_y_deg;         /* perspective: full vertical field of view, (0, 180) */
+    double ortho_height;      /* orthographic: world height of the image, > 0 */
+} rc_camera;
+
+typedef struct {
+    int32_t model;            /* rc_shading_model */
+    int32_t light_is_point;   /* 1: light = world position; 0: direction towards the light */
+    float ka, kd, ks, shininess;
+    float light[3];
+    float grad_eps;           /* > 0: floor of |G| (normalised value per world unit) */
+} rc_shading;
+
+typedef struct {
+    double step;              /* sample distance in world units, > 0 */
+    double clip_lo[3];        /* clip box in world units, intersected with the volume box */
+    double clip_hi[3];
+    float ert_threshold;      /* 0: off; else stop after the first sample with 1-T >= it, (0,1] */
+    int32_t gradient_op;      /* rc_gradient_op */
+    int32_t skip_empty;       /* 1: skip bricks whose samples all have alpha 0 (needs rc_build_bricks) */
+    int32_t reserved;         /* must be 0 */
+} rc_options;
+
+/* Optional per-render counters, accumulated (+=) with device atomics. */
+typedef struct {
+    unsigned long long lattice_samples;   /* sum over hit rays of (index of last sample + 1) */
+    unsigned long long evaluated_samples; /* lattice samples minus those skipped in empty bricks */
+    unsigned long long shaded_samples;    /* samples with alpha != 0 */
+    unsigned long long rays_hit;          /* rays that met the sampling box */
+} rc_stats;
+
+/* Per-pixel side output of a forward render, read by the reverse pass. */
+typedef struct {
+    int32_t k_last;           /* index of the last composited sample, -1 on a miss */
+    float t_final;            /* transmittance after that sample */
+} rc_aux;
+
+/*
+ * Copy a linear voxel grid (Section 2.1, eq. 1; Section 3.1 copies the data
+ * to the GPU) into a new handle that owns a brick-tiled device copy: 8^3
+ * bricks in x-fastest order, voxels inside a brick in Morton order, edge
+ * voxels replicated into the padding.
+ *   src_dev   device pointer, [nz][ny][nx] of dtype; read on `stream`, so it
+ *             must stay valid until the stream has passed this call
+ *   nx,ny,nz  1 .. 4096 each, padded voxel count below 2^31
+ *   spacing   world units between neighbouring voxels, finite and > 0
+ *   vmin,vmax raw values mapped to transfer-function coordinates 0 and 1,
+ *             vmax > vmin
+ *   out       receives the handle (NULL on failure)
+ * Errors: RC_E_INVALID, RC_E_OOM, RC_E_DEVICE.
+ */
+rc_status rc_create_volume(const void* src_dev, int nx, int ny, int nz, rc_dtype dtype,
+                           const double spacing[3], float vmin, float vmax, void* stream,
+                           rc_volume** out);
+
+/* Overwrite the voxels of `vol` from a grid of the same shape and dtype.
+ * If rc_build_bricks ran before, the brick ranges are rebuilt on the same
+ * stream.  Errors: RC_E_INVALID, RC_E_DEVICE. */
+rc_status rc_update_volume(rc_volume* vol, const void* src_dev, void* stream);
+
+/* Build the per-brick value ranges used by empty-space skipping (Section
+ * 5.3): for each 8^3 brick, min and max over the voxels its samples can
+ * touch (the brick plus one voxel on its high side).  brick_edge must be 8
+ * (RC_E_UNSUPPORTED otherwise).  Errors: RC_E_INVALID, RC_E_OOM,
+ * RC_E_DEVICE, RC_E_UNSUPPORTED. */
+rc_status rc_build_bricks(rc_volume* vol, int brick_edge, void* stream);
+
+/*
+ * Render one image (Section 3.10: raycasting, sampling, shading,
+ * compositing).
+ *   tf_rgba_dev  device [tf_len][4] float32 lookup table (Section 3.7),
+ *                indexed by clamp((v-vmin)/(vmax-vmin),0,1)*(tf_len-1) and
+ *                interpolated linearly between entries; 2 <= tf_len <= 65536
+ *   out_rgba_dev device [height][width][4] float32
+ *   aux_dev      NULL or device [height][width] rc_aux
+ *   stats_dev    NULL or a device rc_stats, accumulated
+ * Samples: t_k = t_in + k*step, k = 0..floor((t_out-t_in)/step), from the
+ * entry to the exit of the ray through the volume box intersected with the
+ * clip box.  Each sample: trilinear value, TF colour and opacity a; if a is
+ * not 0, a gradient and the shading model; then C += T a c, T *= (1 - a).
+ * Output (C, 1 - T).  With skip_empty, samples in bricks whose value range
+ * maps to table entries of zero opacity are not evaluated; the image is
+ * unchanged because those samples contribute exactly nothing.
+ * Errors: RC_E_INVALID, RC_E_STATE (skip_empty before rc_build_bricks),
+ * RC_E_OOM, RC_E_DEVICE.
+ */
+rc_status rc_render(const rc_volume* vol, const rc_camera* cam, const float* tf_rgba_dev,
+                    int tf_len, const rc_shading* sh, const rc_options* opt, float* out_rgba_dev,
+                    rc_aux* aux_dev, rc_stats* stats_dev, void* stream);
+
+/*
+ * Reverse mode of rc_render for shading NONE (the renderer's output is then
+ * differentiable in the voxels and the table almost everywhere).
+ *   aux_dev        the rc_aux written by the forward render with the same
+ *                  volume contents, camera, table and options
+ *   grad_rgba_dev  device [height][width][4] float32, dL/d(output)
+ *   grad_volume_dev device [nz][ny][nx] float32, accumulated (+=) with atomics;
+ *                  indices follow the clamp-to-edge rule of the sampling
+ *   grad_tf_dev    device [tf_len][4] float32, accumulated (+=)
+ * The march runs back to front from each ray's last sample and recovers the
+ * transmittance from aux.t_final instead of storing per-sample state.
+ * Errors: RC_E_INVALID, RC_E_UNSUPPORTED (shading model not NONE),
+ * RC_E_DEVICE.
+ */
+rc_status rc_render_backward(const rc_volume* vol, const rc_camera* cam, const float* tf_rgba_dev,
+                             int tf_len, const rc_shading* sh, const rc_options* opt,
+                             const rc_aux* aux_dev, const float* grad_rgba_dev,
+                             float* grad_volume_dev, float* grad_tf_dev, void* stream);
+
+/* Release a handle and its device memory (synchronises with the device).
+ * NULL is ignored. */
+void rc_destroy_volume(rc_volume* vol);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* rc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,292 @@
+"""Python binding of ``librc.so``, the gfx950 volume raycaster.
+
+Argument marshalling only: every step of the render runs in the HIP
+kernels behind the C ABI declared in ``include/rc.h``.  PyTorch provides
+device memory and the current stream.  The functions carry the C names;
+cameras, shading and options are plain dicts with the C struct field
+names (see ``include/rc.h``).  If the shared library is missing the
+import still works, but every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+__all__ = [
+    "RCError", "Volume", "rc_create_volume", "rc_update_volume", "rc_build_bricks",
+    "rc_render", "rc_render_backward", "rc_destroy_volume", "rc_last_error", "RenderFn",
+    "camera_struct", "shading_struct", "options_struct", "library_path",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "librc.so")
+
+RC_OK, RC_E_INVALID, RC_E_OOM, RC_E_DEVICE, RC_E_STATE, RC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+RC_U8, RC_U16, RC_F32 = 0, 1, 2
+GRADIENT_OPS = {"central": 0, "sobel3d": 1, "zucker_hummel": 2}
+SHADING_MODELS = {"none": 0, "blinn_phong": 1, "paper_lambert": 2}
+PROJECTIONS = {"ortho": 0, "persp": 1}
+
+
+class RCError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"rc status {status}: {message}")
+        self.status = status
+
+
+# ---------------------------------------------------------------- C structs
+class rc_camera(C.Structure):
+    _fields_ = [("projection", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("reserved", C.c_int32), ("eye", C.c_double * 3), ("target", C.c_double * 3),
+                ("up", C.c_double * 3), ("fov_y_deg", C.c_double), ("ortho_height", C.c_double)]
+
+
+class rc_shading(C.Structure):
+    _fields_ = [("model", C.c_int32), ("light_is_point", C.c_int32), ("ka", C.c_float),
+                ("kd", C.c_float), ("ks", C.c_float), ("shininess", C.c_float),
+                ("light", C.c_float * 3), ("grad_eps", C.c_float)]
+
+
+class rc_options(C.Structure):
+    _fields_ = [("step", C.c_double), ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3),
+                ("ert_threshold", C.c_float), ("gradient_op", C.c_int32),
+                ("skip_empty", C.c_int32), ("reserved", C.c_int32)]
+
+
+class rc_stats(C.Structure):
+    _fields_ = [("lattice_samples", C.c_ulonglong), ("evaluated_samples", C.c_ulonglong),
+                ("shaded_samples", C.c_ulonglong), ("rays_hit", C.c_ulonglong)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is not built; run __graft_entry__.build() "
+                               "(there is no non-HIP fallback)")
+        L = C.CDLL(_LIB_PATH)
+        vp, cp = C.c_void_p, C.c_char_p
+        L.rc_last_error.restype = cp
+        L.rc_last_error.argtypes = []
+        L.rc_create_volume.restype = C.c_int
+        L.rc_create_volume.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int,
+                                       C.POINTER(C.c_double), C.c_float, C.c_float, vp,
+                                       C.POINTER(vp)]
+        L.rc_update_volume.restype = C.c_int
+        L.rc_update_volume.argtypes = [vp, vp, vp]
+        L.rc_build_bricks.restype = C.c_int
+        L.rc_build_bricks.argtypes = [vp, C.c_int, vp]
+        L.rc_render.restype = C.c_int
+        L.rc_render.argtypes = [vp, C.POINTER(rc_camera), vp, C.c_int, C.POINTER(rc_shading),
+                                C.POINTER(rc_options), vp, vp, vp, vp]
+        L.rc_render_backward.restype = C.c_int
+        L.rc_render_backward.argtypes = [vp, C.POINTER(rc_camera), vp, C.c_int,
+                                         C.POINTER(rc_shading), C.POINTER(rc_options), vp, vp,
+                                         vp, vp, vp]
+        L.rc_destroy_volume.restype = None
+        L.rc_destroy_volume.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def rc_last_error() -> str:
+    return _L().rc_last_error().decode()
+
+
+def _check(st):
+    if st != RC_OK:
+        raise RCError(st, rc_last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ---------------------------------------------------------------- dict -> struct
+def camera_struct(cam: dict) -> rc_camera:
+    return rc_camera(PROJECTIONS[cam["projection"]], int(cam["width"]), int(cam["height"]), 0,
+                     (C.c_double * 3)(*cam["eye"]), (C.c_double * 3)(*cam["target"]),
+                     (C.c_double * 3)(*cam["up"]), float(cam["fov_y_deg"]),
+                     float(cam["ortho_height"]))
+
+
+def shading_struct(sh: dict) -> rc_shading:
+    return rc_shading(SHADING_MODELS[sh["model"]], int(bool(sh["light_is_point"])), sh["ka"],
+                      sh["kd"], sh["ks"], sh["shininess"], (C.c_float * 3)(*sh["light"]),
+                      sh["grad_eps"])
+
+
+def options_struct(opt: dict) -> rc_options:
+    return rc_options(float(opt["step"]), (C.c_double * 3)(*opt["clip_lo"]),
+                      (C.c_double * 3)(*opt["clip_hi"]), float(opt["ert_threshold"]),
+                      GRADIENT_OPS[opt["gradient_op"]], int(bool(opt["skip_empty"])), 0)
+
+
+# ---------------------------------------------------------------- volumes
+_DT = {torch.uint8: RC_U8, torch.uint16: RC_U16, torch.int16: RC_U16, torch.float32: RC_F32}
+
+
+class Volume:
+    """Owns an ``rc_volume*``; keeps the last source tensor alive."""
+
+    def __init__(self, handle, shape_zyx, dtype, spacing, vmin, vmax, src):
+        self.handle = handle
+        self.shape = tuple(shape_zyx)
+        self.dtype = dtype
+        self.spacing = tuple(spacing)
+        self.vmin, self.vmax = vmin, vmax
+        self._src = src
+        self.has_bricks = False
+
+    def __del__(self):
+        try:
+            if self.handle:
+                rc_destroy_volume(self)
+        except Exception:
+            pass
+
+
+def _check_src(src):
+    if not isinstance(src, torch.Tensor) or not src.is_cuda:
+        raise TypeError("volume source must be a CUDA tensor")
+    if src.dim() != 3 or not src.is_contiguous():
+        raise ValueError("volume source must be a contiguous [nz][ny][nx] tensor")
+    if src.dtype not in _DT:
+        raise TypeError(f"unsupported voxel dtype {src.dtype} (uint8, uint16/int16 bits, float32)")
+
+
+def rc_create_volume(src: torch.Tensor, spacing=(1.0, 1.0, 1.0), vmin=0.0, vmax=1.0,
+                     stream=None) -> Volume:
+    _check_src(src)
+    nz, ny, nx = src.shape
+    h = C.c_void_p()
+    sp = (C.c_double * 3)(*spacing)
+    _check(_L().rc_create_volume(_ptr(src), nx, ny, nz, _DT[src.dtype], sp, float(vmin),
+                                 float(vmax), _stream(stream), C.byref(h)))
+    return Volume(h, (nz, ny, nx), _DT[src.dtype], spacing, vmin, vmax, src)
+
+
+def rc_update_volume(vol: Volume, src: torch.Tensor, stream=None):
+    _check_src(src)
+    if tuple(src.shape) != vol.shape or _DT[src.dtype] != vol.dtype:
+        raise ValueError("rc_update_volume: shape/dtype differ from the volume")
+    _check(_L().rc_update_volume(vol.handle, _ptr(src), _stream(stream)))
+    vol._src = src
+
+
+def rc_build_bricks(vol: Volume, brick_edge=8, stream=None):
+    _check(_L().rc_build_bricks(vol.handle, int(brick_edge), _stream(stream)))
+    vol.has_bricks = True
+
+
+def rc_destroy_volume(vol: Volume):
+    if vol.handle:
+        _L().rc_destroy_volume(vol.handle)
+        vol.handle = None
+
+
+# ---------------------------------------------------------------- render
+def _check_tf(tf):
+    if not (isinstance(tf, torch.Tensor) and tf.is_cuda and tf.dtype == torch.float32
+            and tf.dim() == 2 and tf.shape[1] == 4 and tf.is_contiguous()):
+        raise ValueError("transfer function must be a contiguous CUDA float32 [M,4] tensor")
+
+
+def rc_render(vol: Volume, camera: dict, tf: torch.Tensor, shading: dict, options: dict,
+              out: torch.Tensor = None, aux: torch.Tensor = None, stats: torch.Tensor = None,
+              stream=None) -> torch.Tensor:
+    """Render one image; returns ``out`` ([H,W,4] float32).
+
+    ``aux``: optional int64 [H,W] tensor receiving rc_aux records
+    (k_last int32, t_final float32 packed per pixel).  ``stats``: optional
+    int64 [4] tensor accumulating rc_stats."""
+    _check_tf(tf)
+    H, W = int(camera["height"]), int(camera["width"])
+    if out is None:
+        out = torch.empty((H, W, 4), dtype=torch.float32, device=tf.device)
+    if out.shape != (H, W, 4) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [H,W,4] tensor")
+    if aux is not None and (aux.numel() != H * W or aux.element_size() * aux.numel() != 8 * H * W):
+        raise ValueError("aux must hold H*W 8-byte records")
+    if stats is not None and stats.numel() * stats.element_size() != 32:
+        raise ValueError("stats must be 32 bytes (4 counters)")
+    cam, sh, opt = camera_struct(camera), shading_struct(shading), options_struct(options)
+    _check(_L().rc_render(vol.handle, C.byref(cam), _ptr(tf), tf.shape[0], C.byref(sh),
+                          C.byref(opt), _ptr(out), _ptr(aux), _ptr(stats), _stream(stream)))
+    return out
+
+
+def rc_render_backward(vol: Volume, camera: dict, tf: torch.Tensor, shading: dict, options: dict,
+                       aux: torch.Tensor, grad_rgba: torch.Tensor, grad_volume=None, grad_tf=None,
+                       stream=None):
+    """Accumulate dL/dvolume ([nz,ny,nx] float32) and dL/dtf ([M,4]); returns both."""
+    _check_tf(tf)
+    if grad_volume is None:
+        grad_volume = torch.zeros(vol.shape, dtype=torch.float32, device=tf.device)
+    if grad_tf is None:
+        grad_tf = torch.zeros_like(tf)
+    H, W = int(camera["height"]), int(camera["width"])
+    grad_rgba = grad_rgba.contiguous()
+    if grad_rgba.shape != (H, W, 4) or grad_rgba.dtype != torch.float32:
+        raise ValueError("grad_rgba must be float32 [H,W,4]")
+    if grad_volume.shape != vol.shape or grad_volume.dtype != torch.float32:
+        raise ValueError("grad_volume must be float32 with the volume's shape")
+    cam, sh, opt = camera_struct(camera), shading_struct(shading), options_struct(options)
+    _check(_L().rc_render_backward(vol.handle, C.byref(cam), _ptr(tf), tf.shape[0], C.byref(sh),
+                                   C.byref(opt), _ptr(aux), _ptr(grad_rgba), _ptr(grad_volume),
+                                   _ptr(grad_tf), _stream(stream)))
+    return grad_volume, grad_tf
+
+
+def new_aux(camera: dict, device="cuda") -> torch.Tensor:
+    return torch.empty((int(camera["height"]), int(camera["width"])), dtype=torch.int64,
+                       device=device)
+
+
+def aux_fields(aux: torch.Tensor):
+    """(k_last int32 [H,W], t_final float32 [H,W]) views of an aux tensor."""
+    pair = aux.view(torch.int32).view(*aux.shape, 2)
+    return pair[..., 0], pair[..., 1].view(torch.float32)
+
+
+class RenderFn(torch.autograd.Function):
+    """Differentiable unshaded render: (volume float32, tf) -> rgba.
+
+    forward: rc_update_volume with the volume tensor, then rc_render with
+    aux; backward: rc_render_backward (adjoint march, transmittance
+    recovered from aux)."""
+
+    @staticmethod
+    def forward(ctx, volume, tf, handle, camera, shading, options):
+        volume = volume.contiguous()
+        tf = tf.contiguous()
+        rc_update_volume(handle, volume)
+        aux = new_aux(camera, device=tf.device)
+        out = rc_render(handle, camera, tf, shading, options, aux=aux)
+        ctx.save_for_backward(tf, aux)
+        ctx.handle, ctx.camera, ctx.shading, ctx.options = handle, camera, shading, options
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        tf, aux = ctx.saved_tensors
+        gv, gtf = rc_render_backward(ctx.handle, ctx.camera, tf, ctx.shading, ctx.options, aux,
+                                     grad_out.float())
+        return gv, gtf, None, None, None, None

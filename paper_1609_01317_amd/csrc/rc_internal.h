@@ -1,0 +1,107 @@
+// Internal declarations of the raycaster library: the volume handle, error
+// reporting, the brick layout and the parameter block of the render kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdarg>
+#include <cstdio>
+
+#include "../../include/rc.h"
+
+struct rc_volume {
+    int nx, ny, nz;
+    rc_dtype dtype;
+    int elem_bytes;
+    double spacing[3];
+    float vmin, vmax;
+    int nbx, nby, nbz;          // bricks per axis
+    long long nbricks;
+    void* bricked;              // nbricks * 512 voxels of dtype
+    float2* brick_range;        // nbricks (min, max) or null before rc_build_bricks
+    int device;
+};
+
+namespace rc {
+
+// ---------------------------------------------------------------- errors
+rc_status fail(rc_status st, const char* fmt, ...);
+rc_status hip_fail(hipError_t e, const char* what);
+
+#define RC_HIP(call)                                          \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return rc::hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------- brick layout
+// Bricks of 8^3 voxels, bricks in x-fastest order, voxels inside a brick in
+// Morton order (bit i of x, y, z -> bits 3i, 3i+1, 3i+2).  The offset of a
+// voxel is separable: off(x,y,z) = ox(x) + oy(y) + oz(z), so a stencil
+// gathers from 4+4+4 per-axis offsets.
+constexpr int kBrick = 8;
+constexpr int kBrickVox = 512;
+
+__host__ __device__ inline uint32_t spread3(uint32_t v) {
+    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
+}
+__host__ __device__ inline uint32_t compact3(uint32_t m) {
+    return (m & 1u) | ((m >> 2) & 2u) | ((m >> 4) & 4u);
+}
+__host__ __device__ inline int off_x(int x) { return (x >> 3) * kBrickVox + (int)spread3(x & 7); }
+__host__ __device__ inline int off_y(int y, int sy) { return (y >> 3) * sy + ((int)spread3(y & 7) << 1); }
+__host__ __device__ inline int off_z(int z, int sz) { return (z >> 3) * sz + ((int)spread3(z & 7) << 2); }
+
+// ---------------------------------------------------------------- render parameters
+struct RenderParams {
+    // camera frame and image (FP64: ray set-up is exact to double)
+    double eye[3], f[3], r[3], u[3];
+    double tan_half, aspect, ortho_half;
+    int projection, W, H;
+    int tiles_x, n_tiles;
+    // sampling box (world) and lattice
+    double lo[3], hi[3];
+    double step;
+    double inv_s[3];
+    float s[3];
+    // volume (bricked)
+    const void* vox;
+    int nx, ny, nz;
+    int sy, sz;                 // brick-row and brick-slab strides in voxels
+    int nbx, nby, nbz;
+    float vmin, inv_range;
+    // transfer function
+    const float4* tf;
+    int M;
+    float Mm1;
+    // gradient scale: 1 / (gain * spacing_a * (vmax - vmin))
+    float gscale[3];
+    // shading
+    int shade;
+    float ka, kd, ks, shininess;
+    int light_is_point;
+    float light[3];             // position, or unit direction towards the light
+    float grad_eps;
+    // options
+    float tau;
+    int skip;
+    const uint8_t* empty;       // per-brick flag, 1 = every sample has alpha 0
+    // outputs
+    float4* out;
+    rc_aux* aux;
+    rc_stats* stats;
+};
+
+// Host-side preparation shared by the forward, reverse and batch paths.
+rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const float* tf, int tf_len,
+                            const rc_shading* sh, const rc_options* opt);
+void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* cam,
+                        const float* tf, int tf_len, const rc_shading* sh, const rc_options* opt);
+// Launch the prefix + empty-mask kernels into `mask` (nbricks bytes) using
+// `prefix` (tf_len + 1 ints) as scratch.
+rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
+                            int* prefix, hipStream_t st);
+rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
+
+}  // namespace rc

@@ -1,0 +1,341 @@
+// Forward render: argument checks, the per-render empty-brick mask and the
+// raycast kernel (one ray per pixel, Section 3.10).
+#include <cmath>
+
+#include "march.h"
+
+namespace rc {
+
+// ---------------------------------------------------------------- empty mask
+// prefix[i] = number of table entries j < i with alpha != 0 (one workgroup).
+__global__ __launch_bounds__(256) void tf_alpha_prefix(const float4* __restrict__ tf, int M,
+                                                       int* __restrict__ prefix) {
+    __shared__ int part[256];
+    int chunk = (M + 255) / 256;
+    int lo = threadIdx.x * chunk, hi = min(lo + chunk, M);
+    int cnt = 0;
+    for (int i = lo; i < hi; ++i) cnt += tf[i].w != 0.0f;
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int t = 0; t < 256; ++t) {
+            int c = part[t];
+            part[t] = acc;
+            acc += c;
+        }
+        prefix[M] = acc;
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int i = lo; i < hi; ++i) {
+        prefix[i] = acc;
+        acc += tf[i].w != 0.0f;
+    }
+}
+
+// empty[b] = 1 iff every table entry a sample in brick b can interpolate has
+// alpha 0.  The value of such a sample lies in the brick's [min, max], so its
+// table coordinate lies in [u(min), u(max)] (same FP32 mapping as the march,
+// which is monotone); one entry of margin on each side absorbs rounding.
+__global__ __launch_bounds__(256) void empty_mask(const float2* __restrict__ range,
+                                                  const int* __restrict__ prefix, int M,
+                                                  float vmin, float inv_range, float Mm1,
+                                                  uint8_t* __restrict__ empty, long long nbricks) {
+    long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbricks) return;
+    float2 r = range[b];
+    float ulo = fminf(fmaxf((r.x - vmin) * inv_range, 0.0f), 1.0f) * Mm1;
+    float uhi = fminf(fmaxf((r.y - vmin) * inv_range, 0.0f), 1.0f) * Mm1;
+    int ilo = max((int)ulo - 1, 0);
+    int ihi = min((int)uhi + 2, M - 1);
+    empty[b] = (prefix[ihi + 1] - prefix[ilo]) == 0;
+}
+
+rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
+                            int* prefix, hipStream_t st) {
+    float inv_range = (float)(1.0 / ((double)v->vmax - (double)v->vmin));
+    hipLaunchKernelGGL(tf_alpha_prefix, dim3(1), dim3(256), 0, st, (const float4*)tf, tf_len,
+                       prefix);
+    RC_HIP(hipGetLastError());
+    unsigned grid = (unsigned)((v->nbricks + 255) / 256);
+    hipLaunchKernelGGL(empty_mask, dim3(grid), dim3(256), 0, st, v->brick_range, prefix, tf_len,
+                       v->vmin, inv_range, (float)(tf_len - 1), mask, v->nbricks);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+// ---------------------------------------------------------------- the kernel
+// Workgroup = one wave = an 8x8 pixel tile.  Workgroups are dealt to the 8
+// XCDs round-robin; the swizzle gives each XCD a contiguous band of tiles so
+// neighbouring rays share that XCD's L2.
+__device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
+    int q = nb / 8, rem = nb % 8;
+    int xcd = bid % 8, loc = bid / 8;
+    return xcd < rem ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
+}
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename VT, int OP>
+__global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
+    int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+    int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+    int lane = threadIdx.x;
+    int px = tx * 8 + (lane & 7), py = ty * 8 + (lane >> 3);
+    bool valid = px < P.W && py < P.H;
+    MarchOut M;
+    M.rgba = make_float4(0.f, 0.f, 0.f, 0.f);
+    M.k_last = -1;
+    M.T = 1.0f;
+    M.evaluated = M.shaded = 0;
+    Ray R;
+    R.K = -1;
+    if (valid) {
+        setup_ray(P, px, py, R);
+        if (R.K >= 0) march<VT, OP>(P, R, M);
+        long long pix = (long long)py * P.W + px;
+        P.out[pix] = M.rgba;
+        if (P.aux) P.aux[pix] = rc_aux{M.k_last, M.T};
+    }
+    if (P.stats) {
+        unsigned lat = wave_sum(R.K >= 0 ? (unsigned)(M.k_last + 1) : 0u);
+        unsigned ev = wave_sum(M.evaluated);
+        unsigned sh = wave_sum(M.shaded);
+        unsigned hit = wave_sum(R.K >= 0 ? 1u : 0u);
+        if (lane == 0) {
+            atomicAdd(&P.stats->lattice_samples, (unsigned long long)lat);
+            atomicAdd(&P.stats->evaluated_samples, (unsigned long long)ev);
+            atomicAdd(&P.stats->shaded_samples, (unsigned long long)sh);
+            atomicAdd(&P.stats->rays_hit, (unsigned long long)hit);
+        }
+    }
+}
+
+template <typename VT>
+static void launch_fwd_t(const RenderParams& P, int op, hipStream_t st) {
+    dim3 grid((unsigned)P.n_tiles), block(64);
+    if (op == RC_GRAD_CENTRAL)
+        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_CENTRAL>), grid, block, 0, st, P);
+    else if (op == RC_GRAD_SOBEL3D)
+        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_SOBEL3D>), grid, block, 0, st, P);
+    else
+        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_ZUCKER_HUMMEL>), grid, block, 0, st, P);
+}
+
+rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st) {
+    if (dt == RC_U8) launch_fwd_t<uint8_t>(P, op, st);
+    else if (dt == RC_U16) launch_fwd_t<uint16_t>(P, op, st);
+    else launch_fwd_t<float>(P, op, st);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+// ---------------------------------------------------------------- host side
+static bool finite3(const double a[3]) {
+    return std::isfinite(a[0]) && std::isfinite(a[1]) && std::isfinite(a[2]);
+}
+static void normalize3(const double a[3], double out[3]) {
+    double n = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    double s = n > 0.0 ? 1.0 / n : 0.0;
+    out[0] = a[0] * s; out[1] = a[1] * s; out[2] = a[2] * s;
+}
+static void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void sampling_box(const rc_volume* v, const rc_options* opt, double lo[3], double hi[3]) {
+    const int n[3] = {v->nx, v->ny, v->nz};
+    for (int a = 0; a < 3; ++a) {
+        double ext = (n[a] - 1) * v->spacing[a];
+        lo[a] = opt->clip_lo[a] > 0.0 ? opt->clip_lo[a] : 0.0;
+        hi[a] = opt->clip_hi[a] < ext ? opt->clip_hi[a] : ext;
+    }
+}
+
+rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const float* tf, int tf_len,
+                            const rc_shading* sh, const rc_options* opt) {
+    if (!v) return fail(RC_E_INVALID, "volume is NULL");
+    if (!cam) return fail(RC_E_INVALID, "camera is NULL");
+    if (!tf) return fail(RC_E_INVALID, "transfer function is NULL");
+    if (!sh) return fail(RC_E_INVALID, "shading is NULL");
+    if (!opt) return fail(RC_E_INVALID, "options is NULL");
+    if (cam->projection != RC_PERSPECTIVE && cam->projection != RC_ORTHOGRAPHIC)
+        return fail(RC_E_INVALID, "camera: unknown projection %d", cam->projection);
+    if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
+        return fail(RC_E_INVALID, "camera: image %d x %d outside 1..16384", cam->width, cam->height);
+    if (cam->reserved != 0) return fail(RC_E_INVALID, "camera: reserved field must be 0");
+    if (!finite3(cam->eye) || !finite3(cam->target) || !finite3(cam->up))
+        return fail(RC_E_INVALID, "camera: eye/target/up must be finite");
+    double f[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1],
+                   cam->target[2] - cam->eye[2]}, fr[3];
+    normalize3(f, f);
+    cross3(f, cam->up, fr);
+    if (f[0] == 0.0 && f[1] == 0.0 && f[2] == 0.0)
+        return fail(RC_E_INVALID, "camera: eye equals target");
+    if (std::sqrt(fr[0] * fr[0] + fr[1] * fr[1] + fr[2] * fr[2]) < 1e-12)
+        return fail(RC_E_INVALID, "camera: up is parallel to the view direction");
+    if (cam->projection == RC_PERSPECTIVE &&
+        !(std::isfinite(cam->fov_y_deg) && cam->fov_y_deg > 0.0 && cam->fov_y_deg < 180.0))
+        return fail(RC_E_INVALID, "camera: fov_y_deg must be in (0, 180)");
+    if (cam->projection == RC_ORTHOGRAPHIC &&
+        !(std::isfinite(cam->ortho_height) && cam->ortho_height > 0.0))
+        return fail(RC_E_INVALID, "camera: ortho_height must be finite and > 0");
+    if (tf_len < 2 || tf_len > 65536)
+        return fail(RC_E_INVALID, "transfer function length %d outside 2..65536", tf_len);
+    if (sh->model != RC_SHADE_NONE && sh->model != RC_SHADE_BLINN_PHONG &&
+        sh->model != RC_SHADE_PAPER_LAMBERT)
+        return fail(RC_E_INVALID, "shading: unknown model %d", sh->model);
+    if (sh->model != RC_SHADE_NONE) {
+        if (!(std::isfinite(sh->grad_eps) && sh->grad_eps > 0.0f))
+            return fail(RC_E_INVALID, "shading: grad_eps must be finite and > 0");
+        if (!(std::isfinite(sh->ka) && std::isfinite(sh->kd) && std::isfinite(sh->ks) &&
+              std::isfinite(sh->shininess) && sh->shininess >= 0.0f))
+            return fail(RC_E_INVALID, "shading: ka/kd/ks/shininess must be finite, shininess >= 0");
+        if (!(std::isfinite(sh->light[0]) && std::isfinite(sh->light[1]) &&
+              std::isfinite(sh->light[2])))
+            return fail(RC_E_INVALID, "shading: light must be finite");
+        if (!sh->light_is_point && sh->light[0] == 0.0f && sh->light[1] == 0.0f &&
+            sh->light[2] == 0.0f)
+            return fail(RC_E_INVALID, "shading: directional light is the zero vector");
+        if (sh->light_is_point != 0 && sh->light_is_point != 1)
+            return fail(RC_E_INVALID, "shading: light_is_point must be 0 or 1");
+    }
+    if (!(std::isfinite(opt->step) && opt->step > 0.0))
+        return fail(RC_E_INVALID, "options: step must be finite and > 0");
+    if (!(opt->ert_threshold >= 0.0f && opt->ert_threshold <= 1.0f))
+        return fail(RC_E_INVALID, "options: ert_threshold must be in [0, 1]");
+    if (opt->gradient_op != RC_GRAD_CENTRAL && opt->gradient_op != RC_GRAD_SOBEL3D &&
+        opt->gradient_op != RC_GRAD_ZUCKER_HUMMEL)
+        return fail(RC_E_INVALID, "options: unknown gradient operator %d", opt->gradient_op);
+    if (opt->skip_empty != 0 && opt->skip_empty != 1)
+        return fail(RC_E_INVALID, "options: skip_empty must be 0 or 1");
+    if (opt->reserved != 0) return fail(RC_E_INVALID, "options: reserved field must be 0");
+    for (int a = 0; a < 3; ++a)
+        if (std::isnan(opt->clip_lo[a]) || std::isnan(opt->clip_hi[a]))
+            return fail(RC_E_INVALID, "options: clip box has NaN");
+    double lo[3], hi[3];
+    sampling_box(v, opt, lo, hi);
+    double diag2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double e = hi[a] > lo[a] ? hi[a] - lo[a] : 0.0;
+        diag2 += e * e;
+    }
+    if (std::sqrt(diag2) / opt->step > 16777216.0)
+        return fail(RC_E_INVALID, "options: more than 2^24 samples per ray (step too small)");
+    if (opt->skip_empty && !v->brick_range)
+        return fail(RC_E_STATE, "options: skip_empty needs rc_build_bricks first");
+    int dev = -1;
+    if (hipGetDevice(&dev) == hipSuccess && dev != v->device)
+        return fail(RC_E_INVALID, "volume lives on device %d, current device is %d", v->device, dev);
+    return RC_OK;
+}
+
+static double op_gain(int op) {
+    if (op == RC_GRAD_CENTRAL) return 2.0;
+    if (op == RC_GRAD_SOBEL3D) {
+        int s = 0;
+        for (int b = -1; b <= 1; ++b)
+            for (int e = -1; e <= 1; ++e) s += sobel_weight(b, e);
+        return 2.0 * s;
+    }
+    double s = 0.0;
+    for (int b = -1; b <= 1; ++b)
+        for (int e = -1; e <= 1; ++e) s += 1.0 / std::sqrt(1.0 + b * b + e * e);
+    return 2.0 * s;
+}
+
+void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* cam,
+                        const float* tf, int tf_len, const rc_shading* sh, const rc_options* opt) {
+    double tmp[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1],
+                     cam->target[2] - cam->eye[2]};
+    normalize3(tmp, P.f);
+    cross3(P.f, cam->up, tmp);
+    normalize3(tmp, P.r);
+    cross3(P.r, P.f, P.u);
+    for (int a = 0; a < 3; ++a) P.eye[a] = cam->eye[a];
+    P.tan_half = std::tan(cam->fov_y_deg * 0.5 * M_PI / 180.0);
+    P.aspect = (double)cam->width / (double)cam->height;
+    P.ortho_half = cam->ortho_height * 0.5;
+    P.projection = cam->projection;
+    P.W = cam->width;
+    P.H = cam->height;
+    P.tiles_x = (cam->width + 7) / 8;
+    P.n_tiles = P.tiles_x * ((cam->height + 7) / 8);
+    sampling_box(v, opt, P.lo, P.hi);
+    P.step = opt->step;
+    for (int a = 0; a < 3; ++a) {
+        P.inv_s[a] = 1.0 / v->spacing[a];
+        P.s[a] = (float)v->spacing[a];
+    }
+    P.vox = v->bricked;
+    P.nx = v->nx; P.ny = v->ny; P.nz = v->nz;
+    P.sy = v->nbx * kBrickVox;
+    P.sz = v->nbx * v->nby * kBrickVox;
+    P.nbx = v->nbx; P.nby = v->nby; P.nbz = v->nbz;
+    double range = (double)v->vmax - (double)v->vmin;
+    P.vmin = v->vmin;
+    P.inv_range = (float)(1.0 / range);
+    P.tf = (const float4*)tf;
+    P.M = tf_len;
+    P.Mm1 = (float)(tf_len - 1);
+    double gain = op_gain(opt->gradient_op);
+    for (int a = 0; a < 3; ++a) P.gscale[a] = (float)(1.0 / (gain * v->spacing[a] * range));
+    P.shade = sh->model;
+    P.ka = sh->ka; P.kd = sh->kd; P.ks = sh->ks; P.shininess = sh->shininess;
+    P.light_is_point = sh->light_is_point;
+    if (sh->light_is_point) {
+        for (int a = 0; a < 3; ++a) P.light[a] = sh->light[a];
+    } else {
+        double l[3] = {sh->light[0], sh->light[1], sh->light[2]}, ln[3];
+        normalize3(l, ln);
+        for (int a = 0; a < 3; ++a) P.light[a] = (float)ln[a];
+    }
+    P.grad_eps = sh->grad_eps;
+    P.tau = opt->ert_threshold;
+    P.skip = opt->skip_empty;
+    P.empty = nullptr;
+    P.out = nullptr;
+    P.aux = nullptr;
+    P.stats = nullptr;
+}
+
+}  // namespace rc
+
+using namespace rc;
+
+extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const float* tf_rgba_dev,
+                               int tf_len, const rc_shading* sh, const rc_options* opt,
+                               float* out_rgba_dev, rc_aux* aux_dev, rc_stats* stats_dev,
+                               void* stream) {
+    rc_status st = check_render_args(v, cam, tf_rgba_dev, tf_len, sh, opt);
+    if (st != RC_OK) return st;
+    if (!out_rgba_dev) return fail(RC_E_INVALID, "rc_render: out_rgba_dev is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    RenderParams P;
+    fill_render_params(P, v, cam, tf_rgba_dev, tf_len, sh, opt);
+    P.out = (float4*)out_rgba_dev;
+    P.aux = aux_dev;
+    P.stats = stats_dev;
+    void* scratch = nullptr;
+    if (opt->skip_empty) {
+        size_t mask_bytes = ((size_t)v->nbricks + 255) & ~(size_t)255;
+        RC_HIP(hipMallocAsync(&scratch, mask_bytes + sizeof(int) * ((size_t)tf_len + 1), s));
+        uint8_t* mask = (uint8_t*)scratch;
+        int* prefix = (int*)((char*)scratch + mask_bytes);
+        st = launch_empty_mask(v, tf_rgba_dev, tf_len, mask, prefix, s);
+        if (st != RC_OK) { (void)hipFreeAsync(scratch, s); return st; }
+        P.empty = mask;
+    }
+    st = launch_forward(P, v->dtype, opt->gradient_op, s);
+    if (scratch) {
+        hipError_t e = hipFreeAsync(scratch, s);
+        if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    }
+    return st;
+}

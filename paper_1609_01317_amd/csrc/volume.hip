@@ -1,0 +1,205 @@
+// Volume handles: ingest into the brick-tiled layout, per-brick value
+// ranges for empty-space skipping, error reporting.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "rc_internal.h"
+
+namespace rc {
+
+static thread_local std::string g_last_error;
+
+rc_status fail(rc_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+rc_status hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory)
+        return fail(RC_E_OOM, "%s: %s", what, hipGetErrorString(e));
+    return fail(RC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- kernels
+// One thread per voxel of the padded bricked array: voxel m of brick b
+// takes the source voxel at the clamped coordinates, so the padding
+// replicates the edge (Section 2.1: the grid is a 3D array of samples).
+template <typename T>
+__global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* __restrict__ dst,
+                                                  int nx, int ny, int nz, int nbx, int nby,
+                                                  long long total) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    long long b = idx >> 9;
+    uint32_t m = (uint32_t)(idx & 511);
+    int bx = (int)(b % nbx);
+    long long rest = b / nbx;
+    int by = (int)(rest % nby);
+    int bz = (int)(rest / nby);
+    int x = bx * kBrick + (int)compact3(m);
+    int y = by * kBrick + (int)compact3(m >> 1);
+    int z = bz * kBrick + (int)compact3(m >> 2);
+    x = min(x, nx - 1);
+    y = min(y, ny - 1);
+    z = min(z, nz - 1);
+    dst[idx] = src[((long long)z * ny + y) * nx + x];
+}
+
+// One wave per brick: min and max over voxels [b0, b0+8] per axis (the
+// brick plus its one-voxel high apron, clamped to the grid), which is every
+// voxel a trilinear sample inside the brick's cells can touch.
+template <typename T>
+__global__ __launch_bounds__(64) void brick_minmax(const T* __restrict__ vox, float2* __restrict__ out,
+                                                   int nx, int ny, int nz, int nbx, int nby,
+                                                   int sy, int sz, long long nbricks) {
+    long long b = blockIdx.x;
+    if (b >= nbricks) return;
+    int bx = (int)(b % nbx);
+    long long rest = b / nbx;
+    int by = (int)(rest % nby);
+    int bz = (int)(rest / nby);
+    float lo = INFINITY, hi = -INFINITY;
+    for (int q = threadIdx.x; q < 729; q += 64) {
+        int dx = q % 9, dy = (q / 9) % 9, dz = q / 81;
+        int x = min(bx * kBrick + dx, nx - 1);
+        int y = min(by * kBrick + dy, ny - 1);
+        int z = min(bz * kBrick + dz, nz - 1);
+        float v = (float)vox[off_x(x) + off_y(y, sy) + off_z(z, sz)];
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fminf(lo, __shfl_xor(lo, o));
+        hi = fmaxf(hi, __shfl_xor(hi, o));
+    }
+    if (threadIdx.x == 0) out[b] = make_float2(lo, hi);
+}
+
+static int elem_size(rc_dtype dt) { return dt == RC_U8 ? 1 : dt == RC_U16 ? 2 : 4; }
+
+static rc_status launch_tile(rc_volume* v, const void* src, hipStream_t st) {
+    long long total = v->nbricks * kBrickVox;
+    unsigned grid = (unsigned)((total + 255) / 256);
+    switch (v->dtype) {
+        case RC_U8:
+            hipLaunchKernelGGL(brick_tile<uint8_t>, dim3(grid), dim3(256), 0, st,
+                               (const uint8_t*)src, (uint8_t*)v->bricked, v->nx, v->ny, v->nz,
+                               v->nbx, v->nby, total);
+            break;
+        case RC_U16:
+            hipLaunchKernelGGL(brick_tile<uint16_t>, dim3(grid), dim3(256), 0, st,
+                               (const uint16_t*)src, (uint16_t*)v->bricked, v->nx, v->ny, v->nz,
+                               v->nbx, v->nby, total);
+            break;
+        default:
+            hipLaunchKernelGGL(brick_tile<float>, dim3(grid), dim3(256), 0, st,
+                               (const float*)src, (float*)v->bricked, v->nx, v->ny, v->nz,
+                               v->nbx, v->nby, total);
+    }
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+static rc_status launch_minmax(rc_volume* v, hipStream_t st) {
+    int sy = v->nbx * kBrickVox, sz = v->nbx * v->nby * kBrickVox;
+    dim3 grid((unsigned)v->nbricks), block(64);
+    switch (v->dtype) {
+        case RC_U8:
+            hipLaunchKernelGGL(brick_minmax<uint8_t>, grid, block, 0, st,
+                               (const uint8_t*)v->bricked, v->brick_range, v->nx, v->ny, v->nz,
+                               v->nbx, v->nby, sy, sz, v->nbricks);
+            break;
+        case RC_U16:
+            hipLaunchKernelGGL(brick_minmax<uint16_t>, grid, block, 0, st,
+                               (const uint16_t*)v->bricked, v->brick_range, v->nx, v->ny, v->nz,
+                               v->nbx, v->nby, sy, sz, v->nbricks);
+            break;
+        default:
+            hipLaunchKernelGGL(brick_minmax<float>, grid, block, 0, st, (const float*)v->bricked,
+                               v->brick_range, v->nx, v->ny, v->nz, v->nbx, v->nby, sy, sz,
+                               v->nbricks);
+    }
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+}  // namespace rc
+
+using namespace rc;
+
+extern "C" const char* rc_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" rc_status rc_create_volume(const void* src_dev, int nx, int ny, int nz, rc_dtype dtype,
+                                      const double spacing[3], float vmin, float vmax,
+                                      void* stream, rc_volume** out) {
+    if (!out) return fail(RC_E_INVALID, "rc_create_volume: out is NULL");
+    *out = nullptr;
+    if (!src_dev) return fail(RC_E_INVALID, "rc_create_volume: src_dev is NULL");
+    if (!spacing) return fail(RC_E_INVALID, "rc_create_volume: spacing is NULL");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+        return fail(RC_E_INVALID, "rc_create_volume: dims %d x %d x %d outside 1..4096", nx, ny, nz);
+    if (dtype != RC_U8 && dtype != RC_U16 && dtype != RC_F32)
+        return fail(RC_E_INVALID, "rc_create_volume: unknown dtype %d", (int)dtype);
+    for (int a = 0; a < 3; ++a)
+        if (!(std::isfinite(spacing[a]) && spacing[a] > 0.0))
+            return fail(RC_E_INVALID, "rc_create_volume: spacing[%d] must be finite and > 0", a);
+    if (!(std::isfinite(vmin) && std::isfinite(vmax) && vmax > vmin))
+        return fail(RC_E_INVALID, "rc_create_volume: need finite vmin < vmax");
+    int nbx = (nx + 7) / 8, nby = (ny + 7) / 8, nbz = (nz + 7) / 8;
+    long long nbricks = (long long)nbx * nby * nbz;
+    if (nbricks * kBrickVox >= (1LL << 31))
+        return fail(RC_E_INVALID, "rc_create_volume: padded volume exceeds 2^31 voxels");
+    rc_volume* v = new (std::nothrow) rc_volume();
+    if (!v) return fail(RC_E_OOM, "rc_create_volume: host allocation failed");
+    v->nx = nx; v->ny = ny; v->nz = nz;
+    v->dtype = dtype;
+    v->elem_bytes = elem_size(dtype);
+    for (int a = 0; a < 3; ++a) v->spacing[a] = spacing[a];
+    v->vmin = vmin; v->vmax = vmax;
+    v->nbx = nbx; v->nby = nby; v->nbz = nbz;
+    v->nbricks = nbricks;
+    v->brick_range = nullptr;
+    hipError_t e = hipGetDevice(&v->device);
+    if (e != hipSuccess) { delete v; return hip_fail(e, "hipGetDevice"); }
+    e = hipMalloc(&v->bricked, (size_t)nbricks * kBrickVox * v->elem_bytes);
+    if (e != hipSuccess) { delete v; return hip_fail(e, "hipMalloc(bricked volume)"); }
+    rc_status st = launch_tile(v, src_dev, (hipStream_t)stream);
+    if (st != RC_OK) { (void)hipFree(v->bricked); delete v; return st; }
+    *out = v;
+    return RC_OK;
+}
+
+extern "C" rc_status rc_update_volume(rc_volume* v, const void* src_dev, void* stream) {
+    if (!v) return fail(RC_E_INVALID, "rc_update_volume: volume is NULL");
+    if (!src_dev) return fail(RC_E_INVALID, "rc_update_volume: src_dev is NULL");
+    rc_status st = launch_tile(v, src_dev, (hipStream_t)stream);
+    if (st != RC_OK) return st;
+    if (v->brick_range) return launch_minmax(v, (hipStream_t)stream);
+    return RC_OK;
+}
+
+extern "C" rc_status rc_build_bricks(rc_volume* v, int brick_edge, void* stream) {
+    if (!v) return fail(RC_E_INVALID, "rc_build_bricks: volume is NULL");
+    if (brick_edge != kBrick)
+        return fail(RC_E_UNSUPPORTED, "rc_build_bricks: brick edge %d (only 8 is built)", brick_edge);
+    if (!v->brick_range) {
+        hipError_t e = hipMalloc((void**)&v->brick_range, (size_t)v->nbricks * sizeof(float2));
+        if (e != hipSuccess) { v->brick_range = nullptr; return hip_fail(e, "hipMalloc(brick ranges)"); }
+    }
+    return launch_minmax(v, (hipStream_t)stream);
+}
+
+extern "C" void rc_destroy_volume(rc_volume* v) {
+    if (!v) return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(v->bricked);
+    if (v->brick_range) (void)hipFree(v->brick_range);
+    delete v;
+}

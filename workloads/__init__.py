@@ -209,7 +209,7 @@ def orbit_camera(dims_xyz, spacing, azimuth_deg, elevation_deg, width, height,
     """
     ext = (np.asarray(dims_xyz, dtype=np.float64) - 1.0) * np.asarray(spacing, dtype=np.float64)
     centre = ext / 2.0
-    r = float(np.linalg.norm(ext)) / 2.0
+    r = max(float(np.linalg.norm(ext)) / 2.0, 0.5)
     az, el = math.radians(azimuth_deg), math.radians(elevation_deg)
     dirv = np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
     if projection == "persp":
