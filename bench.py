@@ -1,0 +1,274 @@
+"""Benchmark of the volume raycaster on one MI355X.
+
+Headline workload (the paper's 512^3, 16-bit case at 1024^2): a 512^3 u16
+CT-like phantom rendered to 1024x1024 over a 36-view orbit with each of the
+three gradient operators (central difference, Sobel3D, Zucker-Hummel),
+step 0.5, early ray termination at 0.99 and 8^3-brick empty-space skipping.
+
+One step = the whole hot path over that input: re-ingest the resident
+linear volume into the brick layout, rebuild the brick value ranges, then
+108 renders (36 views x 3 operators), each with its own empty-brick mask.
+`value` = lattice samples of one step / step time (Gsamples/s).
+
+Also reported (outside `value`): per-operator rates and frame rates, the
+differentiable form (16 views of a 128^3 f32 volume, forward and
+forward+backward against the plain forward), the dominant kernel's
+roofline position, and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import paper_1609_01317_amd as rc  # noqa: E402
+import workloads as W  # noqa: E402
+
+OPS = ["central", "sobel3d", "zucker_hummel"]
+METRIC = "Gsamples/s fwd and fwd+bwd vs plain, 512³ vol→1024² img; % HBM/L2 roofline"
+
+# Algorithmic work per sample ("Roofline accounting"):
+# every evaluated sample pays the value path (8 voxels, trilinear + table
+# lookup); a sample with alpha != 0 additionally pays the gradient operator,
+# normalisation, shading and compositing.
+FLOPS_VALUE = 28
+FLOPS_SHADED = {"central": 145, "sobel3d": 550, "zucker_hummel": 550}
+VOXELS_VALUE = 8
+VOXELS_SHADED = {"central": 32, "sobel3d": 64, "zucker_hummel": 64}
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def c3_options(sc, op):
+    return dict(sc.options, gradient_op=op)
+
+
+def run_c3(args):
+    sc = W.config_c3(n_views=args.views)
+    log(f"bench: c3 volume {sc.volume.shape} {sc.volume.dtype}, {len(sc.cameras)} views")
+    src = to_dev(sc.volume)
+    vol = rc.rc_create_volume(src, sc.spacing, sc.vmin, sc.vmax)
+    rc.rc_build_bricks(vol, 8)
+    tf = to_dev(sc.tf)
+    out = torch.empty((sc.cameras[0]["height"], sc.cameras[0]["width"], 4),
+                      dtype=torch.float32, device="cuda")
+    opts = {op: c3_options(sc, op) for op in OPS}
+
+    def step(events=None):
+        rc.rc_update_volume(vol, src)
+        rc.rc_build_bricks(vol, 8)
+        for op in OPS:
+            for cam in sc.cameras:
+                if events is not None:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                rc.rc_render(vol, cam, tf, sc.shading, opts[op], out=out)
+                if events is not None:
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e1.record()
+                    events[op].append((e0, e1))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = {op: [] for op in OPS}
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(events)
+        log(f"bench: step {s + 1}/{args.steps} enqueued")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    render_ms = {op: [a.elapsed_time(b) for a, b in events[op]] for op in OPS}
+
+    # untimed counting pass: lattice / evaluated / shaded samples per view
+    counts = {}
+    for op in OPS:
+        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        per_view = []
+        for cam in sc.cameras:
+            st.zero_()
+            rc.rc_render(vol, cam, tf, sc.shading, opts[op], out=out, stats=st)
+            per_view.append(st.cpu().numpy().astype(np.int64))
+        counts[op] = np.array(per_view)
+    torch.cuda.synchronize()
+    return sc, vol, tf, ms_per_step, render_ms, counts
+
+
+def roofline(render_ms, counts):
+    """Dominant kernel: the operator whose renders take the most time."""
+    op = max(OPS, key=lambda o: sum(render_ms[o]))
+    c = counts[op]
+    evaluated, shaded = c[:, 1].astype(float), c[:, 2].astype(float)
+    flops = FLOPS_VALUE * (evaluated - shaded) + FLOPS_SHADED[op] * shaded
+    avg_ms = float(np.mean(render_ms[op]))
+    achieved = float(flops.mean()) / (avg_ms * 1e-3) / 1e12
+    return op, {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "kernel": f"raycast_fwd<uint16, {op}>", "avg_launch_ms": round(avg_ms, 4),
+        "algorithmic_flops_per_launch": float(flops.mean()),
+        "algorithmic_voxel_bytes_per_launch": float(
+            2 * (VOXELS_VALUE * (evaluated - shaded) + VOXELS_SHADED[op] * shaded).mean()),
+    }
+
+
+def run_c5(args):
+    """Differentiable form: 16 views 256^2 of a 128^3 f32 volume, L2 loss."""
+    sc = W.config_c5()
+    vol_t = to_dev(sc.volume)
+    h = rc.rc_create_volume(vol_t, sc.spacing, sc.vmin, sc.vmax)
+    ht = rc.rc_create_volume(to_dev(sc.extra["target_volume"]), sc.spacing, sc.vmin, sc.vmax)
+    tf0 = to_dev(sc.tf)
+    targets = [rc.rc_render(ht, cam, tf0, sc.shading, sc.options).clone() for cam in sc.cameras]
+    vp = vol_t.clone().requires_grad_(True)
+    tp = tf0.clone().requires_grad_(True)
+
+    def fwd_only():
+        with torch.no_grad():
+            rc.rc_update_volume(h, vp.detach())
+            for cam in sc.cameras:
+                rc.rc_render(h, cam, tp.detach(), sc.shading, sc.options)
+
+    def fwd_bwd():
+        loss = 0.0
+        for cam, tgt in zip(sc.cameras, targets):
+            img = rc.RenderFn.apply(vp, tp, h, cam, sc.shading, sc.options)
+            loss = loss + ((img - tgt) ** 2).sum()
+        loss.backward()
+        vp.grad = None
+        tp.grad = None
+
+    def timeit(fn, n):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for cam in sc.cameras:
+        rc.rc_render(h, cam, tf0, sc.shading, sc.options, stats=st)
+    lattice = int(st[0].item())
+    ms_f = timeit(fwd_only, args.c5_iters)
+    ms_fb = timeit(fwd_bwd, args.c5_iters)
+    return {
+        "workload": "128^3 f32 blobs, learnable 256-entry TF, 16 views 256^2, step 0.5, unshaded, "
+                    "L2 loss vs seed-55 target",
+        "lattice_samples": lattice,
+        "fwd_ms": round(ms_f, 3), "fwd_bwd_ms": round(ms_fb, 3),
+        "fwd_gsamples_s": round(lattice / ms_f / 1e6, 3),
+        "fwd_bwd_gsamples_s": round(lattice / ms_fb / 1e6, 3),
+        "fwd_bwd_over_fwd_time": round(ms_fb / ms_f, 2),
+    }
+
+
+def cpu_baseline(sc, counts_unused=None):
+    """FP64 oracle on one full Sobel3D view of the headline workload."""
+    import oracle
+    v = oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
+    cam = sc.cameras[0]
+    opt = c3_options(sc, "sobel3d")
+    t0 = time.perf_counter()
+    r = oracle.render(v, cam, sc.tf, sc.shading, opt)
+    dt = time.perf_counter() - t0
+    lattice = int((r["k_last"] + 1).sum())
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(lattice / dt / 1e9, 6), "unit": "Gsamples/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one full 1024x1024 Sobel3D view (azimuth 0) of the 512^3 u16 orbit: "
+                      f"{lattice} lattice samples in {dt:.1f} s"}
+
+
+def calib_copy():
+    """A plain copy of known size, for scaling HBM counters in a --pmc run."""
+    n = 1 << 28                         # 1 GiB of float32
+    a = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--views", type=int, default=36)
+    ap.add_argument("--c5-iters", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the differentiable form")
+    ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB copy first")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: WORLD_SIZE > 1 is not supported on this one-GPU build", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    if args.calib_copy:
+        calib_copy()
+
+    sc, vol, tf, ms_per_step, render_ms, counts = run_c3(args)
+    lattice_step = int(sum(counts[op][:, 0].sum() for op in OPS))
+    value = lattice_step / (ms_per_step * 1e-3) / 1e9
+    per_op = {}
+    for op in OPS:
+        ms = float(np.sum(render_ms[op])) / args.steps
+        lat = int(counts[op][:, 0].sum())
+        ev = int(counts[op][:, 1].sum())
+        per_op[op] = {"orbit_ms": round(ms, 3), "fps": round(len(sc.cameras) / (ms * 1e-3), 1),
+                      "lattice_gsamples_s": round(lat / (ms * 1e-3) / 1e9, 3),
+                      "evaluated_gsamples_s": round(ev / (ms * 1e-3) / 1e9, 3),
+                      "lattice_samples": lat, "evaluated_samples": ev,
+                      "shaded_samples": int(counts[op][:, 2].sum())}
+    dom_op, roof = roofline(render_ms, counts)
+    result = {
+        "metric": METRIC, "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512^3 u16 CT-like phantom (24 ellipsoids, 12-bit, noise 20) -> "
+                               "1024^2 perspective 60 deg, 36-view orbit at 10 deg steps x "
+                               "{central difference, Sobel3D, Zucker-Hummel}, step 0.5, ERT 0.99, "
+                               "8^3-brick skipping; step = ingest + brick ranges + 108 renders",
+                   "views": len(sc.cameras), "image": [1024, 1024], "volume": [512, 512, 512],
+                   "lattice_samples_per_step": lattice_step},
+        "per_operator": per_op,
+        "roofline": roof,
+    }
+    if not args.no_forms:
+        log("bench: differentiable form")
+        result["differentiable"] = run_c5(args)
+    if not args.no_cpu:
+        log("bench: cpu oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
