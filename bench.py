@@ -184,6 +184,64 @@ def run_c5(args):
     }
 
 
+def run_c4(args):
+    """Batched form: 64 uneven volumes, one persistent launch (graph-replayed)
+    against 64 sequential rc_render launches on the same stream."""
+    scenes = W.config_c4()
+    items = []
+    for sc in scenes:
+        cam = sc.cameras[0]
+        vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+        rc.rc_build_bricks(vol, 8)
+        items.append({"vol": vol, "camera": cam, "tf": to_dev(sc.tf), "shading": sc.shading,
+                      "options": sc.options,
+                      "out": torch.empty((cam["height"], cam["width"], 4), device="cuda")})
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for it in items:
+        rc.rc_render(it["vol"], it["camera"], it["tf"], it["shading"], it["options"], stats=st)
+    lattice = int(st[0].item())
+    os.makedirs(os.path.join(ROOT, "_build"), exist_ok=True)
+    cfg = rc.rc_batch_autotune(items, os.path.join(ROOT, "_build", "batch_autotune.jsonl"))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = rc.rc_batch_create(items, cfg, stream=s)
+
+        def batched():
+            rc.rc_batch_render(b, use_graph=True, stream=s)
+
+        def sequential():
+            for it in items:
+                rc.rc_render(it["vol"], it["camera"], it["tf"], it["shading"], it["options"],
+                             out=it["out"], stream=s)
+
+        def timeit(fn, n):
+            for _ in range(2):
+                fn()
+            s.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(n):
+                fn()
+            e1.record(s)
+            s.synchronize()
+            return e0.elapsed_time(e1) / n
+
+        ms_b = timeit(batched, args.c4_iters)
+        ms_s = timeit(sequential, args.c4_iters)
+        rc.rc_batch_destroy(b)
+    return {
+        "workload": "64 volumes 32^3..256x256x96 u8/u16 (blobs or phantoms), own perspective "
+                    "camera, square images 128..512, own 256-entry TF, CD, Blinn-Phong, ERT 0.99, "
+                    "skip",
+        "lattice_samples": lattice, "autotuned_config": cfg,
+        "batch_graph_ms": round(ms_b, 3), "sequential_64_ms": round(ms_s, 3),
+        "batch_gsamples_s": round(lattice / ms_b / 1e6, 3),
+        "sequential_gsamples_s": round(lattice / ms_s / 1e6, 3),
+        "speedup_vs_sequential": round(ms_s / ms_b, 2),
+    }
+
+
 def cpu_baseline(sc, counts_unused=None):
     """FP64 oracle on one full Sobel3D view of the headline workload."""
     import oracle
@@ -218,6 +276,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--views", type=int, default=36)
     ap.add_argument("--c5-iters", type=int, default=5)
+    ap.add_argument("--c4-iters", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the differentiable form")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB copy first")
@@ -264,6 +323,8 @@ def main():
     if not args.no_forms:
         log("bench: differentiable form")
         result["differentiable"] = run_c5(args)
+        log("bench: batched form")
+        result["batched"] = run_c4(args)
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
         result["cpu_baseline"] = cpu_baseline(sc)

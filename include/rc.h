@@ -183,6 +183,67 @@ rc_status rc_render_backward(const rc_volume* vol, const rc_camera* cam, const f
                              const rc_aux* aux_dev, const float* grad_rgba_dev,
                              float* grad_volume_dev, float* grad_tf_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched rendering: many volumes of uneven size, each with its own camera,
+ * image size and table, rendered by ONE persistent kernel launch.  Each
+ * item is exactly the argument set of one rc_render call and produces the
+ * same image.  Workgroups stay resident and pull (item, tile) work units from
+ * a device queue, so small images share the GPU instead of each leaving it
+ * mostly idle; the launch can be captured once into a HIP graph and replayed.
+ * (Not in the paper: Section 3.10's per-pixel independence is what allows
+ * rays of different images to share one launch.)
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const rc_volume* vol;
+    rc_camera cam;
+    const float* tf_rgba_dev;   /* device [tf_len][4] */
+    int32_t tf_len;
+    int32_t reserved;           /* must be 0 */
+    rc_shading sh;
+    rc_options opt;
+    float* out_rgba_dev;        /* device [height][width][4] */
+    rc_aux* aux_dev;            /* NULL or device [height][width] */
+} rc_batch_item;
+
+/* Launch shape of the persistent kernel. */
+typedef struct {
+    int32_t tile_w;             /* tile width in pixels: 4, 8, 16 or 32 (tiles hold 64 pixels) */
+    int32_t waves_per_wg;       /* waves per workgroup: 1, 2 or 4 */
+    int32_t wg_per_cu;          /* resident workgroups per compute unit: 1 .. 32 */
+    int32_t order;              /* 0: items in the given order; 1: largest images first */
+} rc_batch_config;
+
+typedef struct rc_batch rc_batch;   /* opaque: descriptors, queue, masks, captured graph */
+
+/* Validate every item as rc_render would, upload the descriptors and
+ * allocate the queue and mask scratch.  cfg NULL = {8, 1, 8, 1}.  The
+ * items' volumes, tables and outputs must outlive the batch.
+ * Errors: RC_E_INVALID (with the failing item index in rc_last_error),
+ * RC_E_STATE, RC_E_OOM, RC_E_DEVICE. */
+rc_status rc_batch_create(const rc_batch_item* items, int n, const rc_batch_config* cfg,
+                          void* stream, rc_batch** out);
+
+/* Render every item with one persistent launch (plus two small mask
+ * kernels and a queue reset).  use_graph = 1 captures that sequence into a
+ * HIP graph on the first call and replays it afterwards (stream must not be
+ * NULL); use_graph = 0 launches eagerly.  Errors: RC_E_INVALID, RC_E_DEVICE. */
+rc_status rc_batch_render(rc_batch* b, int use_graph, void* stream);
+
+void rc_batch_destroy(rc_batch* b);
+
+/* create + render (eager) + destroy: one call for one-off batches. */
+rc_status rc_render_batch(const rc_batch_item* items, int n, const rc_batch_config* cfg,
+                          void* stream);
+
+/* Time candidate launch shapes (tile width, waves per workgroup, resident
+ * workgroups, order) on these items and return the fastest in *out.  If
+ * cache_path is not NULL, results are kept there as JSON lines keyed by a
+ * hash of the items' shapes; a hit returns without timing.  Renders into
+ * the items' outputs while timing.  Synchronises `stream`.
+ * Errors: as rc_batch_create, plus RC_E_INVALID for an unwritable cache. */
+rc_status rc_batch_autotune(const rc_batch_item* items, int n, const char* cache_path,
+                            void* stream, rc_batch_config* out);
+
 /* Release a handle and its device memory (synchronises with the device).
  * NULL is ignored. */
 void rc_destroy_volume(rc_volume* vol);

@@ -18,6 +18,8 @@ __all__ = [
     "RCError", "Volume", "rc_create_volume", "rc_update_volume", "rc_build_bricks",
     "rc_render", "rc_render_backward", "rc_destroy_volume", "rc_last_error", "RenderFn",
     "camera_struct", "shading_struct", "options_struct", "library_path",
+    "Batch", "rc_batch_create", "rc_batch_render", "rc_batch_destroy", "rc_render_batch",
+    "rc_batch_autotune",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,6 +62,17 @@ class rc_stats(C.Structure):
                 ("shaded_samples", C.c_ulonglong), ("rays_hit", C.c_ulonglong)]
 
 
+class rc_batch_item(C.Structure):
+    _fields_ = [("vol", C.c_void_p), ("cam", rc_camera), ("tf_rgba_dev", C.c_void_p),
+                ("tf_len", C.c_int32), ("reserved", C.c_int32), ("sh", rc_shading),
+                ("opt", rc_options), ("out_rgba_dev", C.c_void_p), ("aux_dev", C.c_void_p)]
+
+
+class rc_batch_config(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("waves_per_wg", C.c_int32), ("wg_per_cu", C.c_int32),
+                ("order", C.c_int32)]
+
+
 _lib = None
 
 
@@ -94,6 +107,17 @@ def _L():
                                          vp, vp, vp]
         L.rc_destroy_volume.restype = None
         L.rc_destroy_volume.argtypes = [vp]
+        bi, bc = C.POINTER(rc_batch_item), C.POINTER(rc_batch_config)
+        L.rc_batch_create.restype = C.c_int
+        L.rc_batch_create.argtypes = [bi, C.c_int, bc, vp, C.POINTER(vp)]
+        L.rc_batch_render.restype = C.c_int
+        L.rc_batch_render.argtypes = [vp, C.c_int, vp]
+        L.rc_batch_destroy.restype = None
+        L.rc_batch_destroy.argtypes = [vp]
+        L.rc_render_batch.restype = C.c_int
+        L.rc_render_batch.argtypes = [bi, C.c_int, bc, vp]
+        L.rc_batch_autotune.restype = C.c_int
+        L.rc_batch_autotune.argtypes = [bi, C.c_int, C.c_char_p, vp, bc]
         _lib = L
     return _lib
 
@@ -290,3 +314,76 @@ class RenderFn(torch.autograd.Function):
         gv, gtf = rc_render_backward(ctx.handle, ctx.camera, tf, ctx.shading, ctx.options, aux,
                                      grad_out.float())
         return gv, gtf, None, None, None, None
+
+
+# ---------------------------------------------------------------- batches
+def _batch_items(items):
+    """items: list of dicts with keys vol, camera, tf, shading, options, out, aux (optional)."""
+    arr = (rc_batch_item * len(items))()
+    keep = []
+    for i, it in enumerate(items):
+        _check_tf(it["tf"])
+        cam = it["camera"]
+        H, W = int(cam["height"]), int(cam["width"])
+        out = it["out"]
+        if out.shape != (H, W, 4) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError(f"item {i}: out must be a contiguous float32 [H,W,4] tensor")
+        aux = it.get("aux")
+        arr[i] = rc_batch_item(it["vol"].handle, camera_struct(cam), it["tf"].data_ptr(),
+                               it["tf"].shape[0], 0, shading_struct(it["shading"]),
+                               options_struct(it["options"]), out.data_ptr(),
+                               aux.data_ptr() if aux is not None else None)
+        keep.append((it["vol"], it["tf"], out, aux))
+    return arr, keep
+
+
+def _config(cfg):
+    if cfg is None:
+        return None
+    return C.byref(rc_batch_config(int(cfg["tile_w"]), int(cfg["waves_per_wg"]),
+                                   int(cfg["wg_per_cu"]), int(cfg["order"])))
+
+
+class Batch:
+    """Owns an ``rc_batch*`` and keeps its items' tensors alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        try:
+            rc_batch_destroy(self)
+        except Exception:
+            pass
+
+
+def rc_batch_create(items, config=None, stream=None) -> Batch:
+    arr, keep = _batch_items(items)
+    h = C.c_void_p()
+    _check(_L().rc_batch_create(arr, len(items), _config(config), _stream(stream), C.byref(h)))
+    return Batch(h, keep)
+
+
+def rc_batch_render(batch: Batch, use_graph=False, stream=None):
+    _check(_L().rc_batch_render(batch.handle, int(bool(use_graph)), _stream(stream)))
+
+
+def rc_batch_destroy(batch: Batch):
+    if batch.handle:
+        _L().rc_batch_destroy(batch.handle)
+        batch.handle = None
+
+
+def rc_render_batch(items, config=None, stream=None):
+    arr, keep = _batch_items(items)
+    _check(_L().rc_render_batch(arr, len(items), _config(config), _stream(stream)))
+
+
+def rc_batch_autotune(items, cache_path=None, stream=None) -> dict:
+    arr, keep = _batch_items(items)
+    out = rc_batch_config()
+    path = cache_path.encode() if cache_path else None
+    _check(_L().rc_batch_autotune(arr, len(items), path, _stream(stream), C.byref(out)))
+    return {"tile_w": out.tile_w, "waves_per_wg": out.waves_per_wg, "wg_per_cu": out.wg_per_cu,
+            "order": out.order}

@@ -1,0 +1,436 @@
+// Batched rendering: many images of many volumes in one persistent launch.
+// Each item is the argument set of one rc_render call.  Resident waves pull
+// (item, tile) work units from a device counter until the queue is empty;
+// the per-item empty-brick masks are built by two batched kernels; the
+// whole sequence can be captured into a HIP graph and replayed.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "march.h"
+
+namespace rc {
+
+struct MaskJob {
+    const float2* range;
+    const float4* tf;
+    int M;
+    float vmin, inv_range, Mm1;
+    long long nbricks;
+    long long brick_off;        // offset into the concatenated mask array
+    long long prefix_off;       // offset into the concatenated prefix array
+};
+
+// ---------------------------------------------------------------- kernels
+__global__ void batch_reset(int* counter) { *counter = 0; }
+
+// one workgroup per mask job: prefix counts of non-zero table opacities
+__global__ __launch_bounds__(256) void batch_prefix(const MaskJob* __restrict__ jobs,
+                                                    int* __restrict__ prefix_all) {
+    __shared__ int part[256];
+    const MaskJob& J = jobs[blockIdx.x];
+    int* prefix = prefix_all + J.prefix_off;
+    int M = J.M;
+    int chunk = (M + 255) / 256;
+    int lo = threadIdx.x * chunk, hi = min(lo + chunk, M);
+    int cnt = 0;
+    for (int i = lo; i < hi; ++i) cnt += J.tf[i].w != 0.0f;
+    part[threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int t = 0; t < 256; ++t) {
+            int c = part[t];
+            part[t] = acc;
+            acc += c;
+        }
+        prefix[M] = acc;
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int i = lo; i < hi; ++i) {
+        prefix[i] = acc;
+        acc += J.tf[i].w != 0.0f;
+    }
+}
+
+// one thread per brick of every mask job (same rule as empty_mask)
+__global__ __launch_bounds__(256) void batch_mask(const MaskJob* __restrict__ jobs, int njobs,
+                                                  long long total, const int* __restrict__ prefix_all,
+                                                  uint8_t* __restrict__ mask_all) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (jobs[mid].brick_off <= g) lo = mid; else hi = mid;
+    }
+    const MaskJob& J = jobs[lo];
+    long long b = g - J.brick_off;
+    if (b < 0 || b >= J.nbricks) return;
+    const int* prefix = prefix_all + J.prefix_off;
+    float2 r = J.range[b];
+    float ulo = fminf(fmaxf((r.x - J.vmin) * J.inv_range, 0.0f), 1.0f) * J.Mm1;
+    float uhi = fminf(fmaxf((r.y - J.vmin) * J.inv_range, 0.0f), 1.0f) * J.Mm1;
+    int ilo = max((int)ulo - 1, 0);
+    int ihi = min((int)uhi + 2, J.M - 1);
+    mask_all[g] = (prefix[ihi + 1] - prefix[ilo]) == 0;
+}
+
+// The persistent kernel.  `kind` = dtype * 3 + gradient operator selects the
+// instantiation per work unit (uniform across the wave).
+__global__ __launch_bounds__(256) void raycast_batch(const RenderParams* __restrict__ items,
+                                                     const int* __restrict__ kinds,
+                                                     const int* __restrict__ tile_off,
+                                                     const int* __restrict__ order, int n,
+                                                     int total, int* __restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int w = 0;
+        if (lane == 0) w = atomicAdd(counter, 1);
+        w = __builtin_amdgcn_readfirstlane(__shfl(w, 0));
+        if (w >= total) break;
+        int lo = 0, hi = n;
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (tile_off[mid] <= w) lo = mid; else hi = mid;
+        }
+        int item = __builtin_amdgcn_readfirstlane(order[lo]);
+        int tile = w - tile_off[lo];
+        const RenderParams& P = items[item];
+        switch (kinds[item]) {
+            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL>(P, tile, lane); break;
+            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D>(P, tile, lane); break;
+            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane); break;
+            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL>(P, tile, lane); break;
+            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D>(P, tile, lane); break;
+            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane); break;
+            case 6: render_tile<float, RC_GRAD_CENTRAL>(P, tile, lane); break;
+            case 7: render_tile<float, RC_GRAD_SOBEL3D>(P, tile, lane); break;
+            default: render_tile<float, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane); break;
+        }
+    }
+}
+
+}  // namespace rc
+
+using namespace rc;
+
+struct rc_batch {
+    int n;
+    int device;
+    rc_batch_config cfg;
+    int total_tiles;
+    int n_jobs;
+    long long total_bricks;
+    int grid;
+    void* dmem;                 // one allocation holding everything below
+    RenderParams* d_items;
+    int* d_kinds;
+    int* d_tile_off;
+    int* d_order;
+    int* d_counter;
+    MaskJob* d_jobs;
+    int* d_prefix;
+    uint8_t* d_mask;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool captured;
+};
+
+static rc_status check_config(const rc_batch_config& c) {
+    if (c.tile_w != 4 && c.tile_w != 8 && c.tile_w != 16 && c.tile_w != 32)
+        return fail(RC_E_INVALID, "batch config: tile_w must be 4, 8, 16 or 32");
+    if (c.waves_per_wg != 1 && c.waves_per_wg != 2 && c.waves_per_wg != 4)
+        return fail(RC_E_INVALID, "batch config: waves_per_wg must be 1, 2 or 4");
+    if (c.wg_per_cu < 1 || c.wg_per_cu > 32)
+        return fail(RC_E_INVALID, "batch config: wg_per_cu must be 1..32");
+    if (c.order != 0 && c.order != 1) return fail(RC_E_INVALID, "batch config: order must be 0/1");
+    return RC_OK;
+}
+
+static rc_batch_config default_config() { return rc_batch_config{8, 1, 8, 1}; }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc_batch_config* cfg,
+                                     void* stream, rc_batch** out) {
+    if (!out) return fail(RC_E_INVALID, "rc_batch_create: out is NULL");
+    *out = nullptr;
+    if (!items || n < 1 || n > 65536) return fail(RC_E_INVALID, "rc_batch_create: need 1..65536 items");
+    rc_batch_config c = cfg ? *cfg : default_config();
+    rc_status st = check_config(c);
+    if (st != RC_OK) return st;
+    std::vector<RenderParams> P(n);
+    std::vector<int> kinds(n), tiles(n);
+    std::vector<MaskJob> jobs;
+    long long total_bricks = 0, total_prefix = 0;
+    for (int i = 0; i < n; ++i) {
+        const rc_batch_item& it = items[i];
+        st = check_render_args(it.vol, &it.cam, it.tf_rgba_dev, it.tf_len, &it.sh, &it.opt);
+        if (st != RC_OK) return fail(st, "item %d: %s", i, rc_last_error());
+        if (!it.out_rgba_dev) return fail(RC_E_INVALID, "item %d: out_rgba_dev is NULL", i);
+        if (it.reserved != 0) return fail(RC_E_INVALID, "item %d: reserved field must be 0", i);
+        fill_render_params(P[i], it.vol, &it.cam, it.tf_rgba_dev, it.tf_len, &it.sh, &it.opt);
+        set_tiling(P[i], c.tile_w);
+        P[i].out = (float4*)it.out_rgba_dev;
+        P[i].aux = it.aux_dev;
+        kinds[i] = (int)it.vol->dtype * 3 + it.opt.gradient_op;
+        tiles[i] = P[i].n_tiles;
+        if (it.opt.skip_empty) {
+            MaskJob J;
+            J.range = it.vol->brick_range;
+            J.tf = (const float4*)it.tf_rgba_dev;
+            J.M = it.tf_len;
+            J.vmin = it.vol->vmin;
+            J.inv_range = (float)(1.0 / ((double)it.vol->vmax - (double)it.vol->vmin));
+            J.Mm1 = (float)(it.tf_len - 1);
+            J.nbricks = it.vol->nbricks;
+            J.brick_off = total_bricks;
+            J.prefix_off = total_prefix;
+            total_bricks += J.nbricks;
+            total_prefix += it.tf_len + 1;
+            jobs.push_back(J);
+        }
+    }
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    if (c.order == 1)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return tiles[a] > tiles[b]; });
+    std::vector<int> tile_off(n + 1, 0);
+    long long total = 0;
+    for (int q = 0; q < n; ++q) {
+        tile_off[q] = (int)total;
+        total += tiles[order[q]];
+    }
+    tile_off[n] = (int)total;
+    if (total >= (1LL << 31)) return fail(RC_E_INVALID, "rc_batch_create: too many tiles");
+
+    size_t o_items = 0;
+    size_t o_kinds = align256(o_items + sizeof(RenderParams) * n);
+    size_t o_toff = align256(o_kinds + sizeof(int) * n);
+    size_t o_order = align256(o_toff + sizeof(int) * (n + 1));
+    size_t o_counter = align256(o_order + sizeof(int) * n);
+    size_t o_jobs = align256(o_counter + sizeof(int));
+    size_t o_prefix = align256(o_jobs + sizeof(MaskJob) * std::max<size_t>(jobs.size(), 1));
+    size_t o_mask = align256(o_prefix + sizeof(int) * std::max<long long>(total_prefix, 1));
+    size_t bytes = align256(o_mask + std::max<long long>(total_bricks, 1));
+
+    rc_batch* b = new (std::nothrow) rc_batch();
+    if (!b) return fail(RC_E_OOM, "rc_batch_create: host allocation failed");
+    b->n = n;
+    b->cfg = c;
+    b->total_tiles = (int)total;
+    b->n_jobs = (int)jobs.size();
+    b->total_bricks = total_bricks;
+    b->captured = false;
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipMalloc(&b->dmem, bytes);
+    if (e != hipSuccess) { delete b; return hip_fail(e, "rc_batch_create: hipMalloc"); }
+    char* base = (char*)b->dmem;
+    b->d_items = (RenderParams*)(base + o_items);
+    b->d_kinds = (int*)(base + o_kinds);
+    b->d_tile_off = (int*)(base + o_toff);
+    b->d_order = (int*)(base + o_order);
+    b->d_counter = (int*)(base + o_counter);
+    b->d_jobs = (MaskJob*)(base + o_jobs);
+    b->d_prefix = (int*)(base + o_prefix);
+    b->d_mask = (uint8_t*)(base + o_mask);
+    for (int i = 0, j = 0; i < n; ++i)
+        if (items[i].opt.skip_empty) P[i].empty = b->d_mask + jobs[j++].brick_off;
+    hipStream_t s = (hipStream_t)stream;
+    e = hipMemcpyAsync(b->d_items, P.data(), sizeof(RenderParams) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_kinds, kinds.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_tile_off, tile_off.data(), sizeof(int) * (n + 1),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !jobs.empty())
+        e = hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(MaskJob) * jobs.size(),
+                           hipMemcpyHostToDevice, s);
+    // the host vectors go out of scope: wait for the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(b->dmem);
+        delete b;
+        return hip_fail(e, "rc_batch_create: upload");
+    }
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    if (e != hipSuccess || cus < 1) cus = 256;
+    b->grid = cus * c.wg_per_cu;
+    *out = b;
+    return RC_OK;
+}
+
+static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, b->d_counter);
+    if (b->n_jobs > 0) {
+        hipLaunchKernelGGL(batch_prefix, dim3(b->n_jobs), dim3(256), 0, s, b->d_jobs, b->d_prefix);
+        unsigned g = (unsigned)((b->total_bricks + 255) / 256);
+        hipLaunchKernelGGL(batch_mask, dim3(g), dim3(256), 0, s, b->d_jobs, b->n_jobs,
+                           b->total_bricks, b->d_prefix, b->d_mask);
+    }
+    hipLaunchKernelGGL(raycast_batch, dim3(b->grid), dim3(64 * b->cfg.waves_per_wg), 0, s,
+                       b->d_items, b->d_kinds, b->d_tile_off, b->d_order, b->n, b->total_tiles,
+                       b->d_counter);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+extern "C" rc_status rc_batch_render(rc_batch* b, int use_graph, void* stream) {
+    if (!b) return fail(RC_E_INVALID, "rc_batch_render: batch is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!use_graph) return enqueue_batch(b, s);
+    if (!s) return fail(RC_E_INVALID, "rc_batch_render: graph mode needs a non-NULL stream");
+    if (!b->captured) {
+        RC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        rc_status st = enqueue_batch(b, s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (st != RC_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+        b->graph = g;
+        b->captured = true;
+    }
+    RC_HIP(hipGraphLaunch(b->exec, s));
+    return RC_OK;
+}
+
+extern "C" void rc_batch_destroy(rc_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->captured) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+    }
+    (void)hipFree(b->dmem);
+    delete b;
+}
+
+extern "C" rc_status rc_render_batch(const rc_batch_item* items, int n, const rc_batch_config* cfg,
+                                     void* stream) {
+    rc_batch* b = nullptr;
+    rc_status st = rc_batch_create(items, n, cfg, stream, &b);
+    if (st != RC_OK) return st;
+    st = rc_batch_render(b, 0, stream);
+    rc_batch_destroy(b);
+    return st;
+}
+
+// ---------------------------------------------------------------- autotuner
+static unsigned long long fnv1a(const std::string& s) {
+    unsigned long long h = 1469598103934665603ULL;
+    for (unsigned char ch : s) {
+        h ^= ch;
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+static std::string batch_key(const rc_batch_item* items, int n) {
+    std::string k = "v1;n=" + std::to_string(n) + ";";
+    for (int i = 0; i < n; ++i) {
+        const rc_batch_item& it = items[i];
+        k += std::to_string(it.vol->nx) + "x" + std::to_string(it.vol->ny) + "x" +
+             std::to_string(it.vol->nz) + ":" + std::to_string((int)it.vol->dtype) + ":" +
+             std::to_string(it.cam.width) + "x" + std::to_string(it.cam.height) + ":" +
+             std::to_string(it.opt.gradient_op) + ":" + std::to_string(it.sh.model) + ":" +
+             std::to_string(it.opt.skip_empty) + ";";
+    }
+    char buf[32];
+    snprintf(buf, sizeof buf, "%016llx", fnv1a(k));
+    return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, rc_batch_config* out) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    std::string needle = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, needle.c_str())) continue;
+        rc_batch_config c;
+        const char* p = strstr(line, "\"tile_w\":");
+        const char* q = strstr(line, "\"waves_per_wg\":");
+        const char* r = strstr(line, "\"wg_per_cu\":");
+        const char* o = strstr(line, "\"order\":");
+        if (p && q && r && o && sscanf(p, "\"tile_w\": %d", &c.tile_w) == 1 &&
+            sscanf(q, "\"waves_per_wg\": %d", &c.waves_per_wg) == 1 &&
+            sscanf(r, "\"wg_per_cu\": %d", &c.wg_per_cu) == 1 &&
+            sscanf(o, "\"order\": %d", &c.order) == 1 && check_config(c) == RC_OK) {
+            *out = c;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+extern "C" rc_status rc_batch_autotune(const rc_batch_item* items, int n, const char* cache_path,
+                                       void* stream, rc_batch_config* out) {
+    if (!out) return fail(RC_E_INVALID, "rc_batch_autotune: out is NULL");
+    if (!items || n < 1) return fail(RC_E_INVALID, "rc_batch_autotune: no items");
+    for (int i = 0; i < n; ++i)
+        if (!items[i].vol) return fail(RC_E_INVALID, "item %d: volume is NULL", i);
+    std::string key = batch_key(items, n);
+    if (cache_path && cache_lookup(cache_path, key, out)) return RC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int tws[] = {8, 16, 4};
+    const int wpw[] = {1, 4};
+    const int wpc[] = {4, 8, 16};
+    const int ords[] = {1, 0};
+    rc_batch_config best = default_config();
+    float best_ms = INFINITY;
+    hipEvent_t e0, e1;
+    RC_HIP(hipEventCreate(&e0));
+    RC_HIP(hipEventCreate(&e1));
+    rc_status st = RC_OK;
+    for (int tw : tws)
+        for (int w : wpw)
+            for (int pc : wpc)
+                for (int od : ords) {
+                    rc_batch_config c{tw, w, std::max(1, pc / w), od};
+                    rc_batch* b = nullptr;
+                    st = rc_batch_create(items, n, &c, stream, &b);
+                    if (st != RC_OK) goto done;
+                    float ms = 0.0f;
+                    st = enqueue_batch(b, s);                       // warm-up
+                    if (st == RC_OK && hipEventRecord(e0, s) != hipSuccess) st = RC_E_DEVICE;
+                    for (int r = 0; r < 3 && st == RC_OK; ++r) st = enqueue_batch(b, s);
+                    if (st == RC_OK && hipEventRecord(e1, s) != hipSuccess) st = RC_E_DEVICE;
+                    if (st == RC_OK && hipEventSynchronize(e1) != hipSuccess) st = RC_E_DEVICE;
+                    if (st == RC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = RC_E_DEVICE;
+                    rc_batch_destroy(b);
+                    if (st != RC_OK) { fail(st, "rc_batch_autotune: timing failed"); goto done; }
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = c;
+                    }
+                }
+    *out = best;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (!f) { st = fail(RC_E_INVALID, "rc_batch_autotune: cannot write %s", cache_path); goto done; }
+        fprintf(f,
+                "{\"key\": \"%s\", \"tile_w\": %d, \"waves_per_wg\": %d, \"wg_per_cu\": %d, "
+                "\"order\": %d, \"ms_per_batch\": %.4f, \"items\": %d}\n",
+                key.c_str(), best.tile_w, best.waves_per_wg, best.wg_per_cu, best.order,
+                best_ms / 3.0f, n);
+        fclose(f);
+    }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}

@@ -354,4 +354,46 @@ __device__ inline void march(const RenderParams& P, const Ray& R, MarchOut& M) {
     M.shaded = shaded;
 }
 
+// ---------------------------------------------------------------- one tile
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One wave renders one tile of tile_w x (64 / tile_w) pixels; `tile` is the
+// tile's row-major index in the image.  Lanes outside the image idle.
+template <typename VT, int OP>
+__device__ inline void render_tile(const RenderParams& P, int tile, int lane) {
+    const int tw = P.tile_w, th = 64 / P.tile_w;
+    int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+    int px = tx * tw + (lane % tw), py = ty * th + (lane / tw);
+    bool valid = px < P.W && py < P.H;
+    MarchOut M;
+    M.rgba = make_float4(0.f, 0.f, 0.f, 0.f);
+    M.k_last = -1;
+    M.T = 1.0f;
+    M.evaluated = M.shaded = 0;
+    Ray R;
+    R.K = -1;
+    if (valid) {
+        setup_ray(P, px, py, R);
+        if (R.K >= 0) march<VT, OP>(P, R, M);
+        long long pix = (long long)py * P.W + px;
+        P.out[pix] = M.rgba;
+        if (P.aux) P.aux[pix] = rc_aux{M.k_last, M.T};
+    }
+    if (P.stats) {
+        unsigned lat = wave_sum(R.K >= 0 ? (unsigned)(M.k_last + 1) : 0u);
+        unsigned ev = wave_sum(M.evaluated);
+        unsigned sh = wave_sum(M.shaded);
+        unsigned hit = wave_sum(R.K >= 0 ? 1u : 0u);
+        if (lane == 0) {
+            atomicAdd(&P.stats->lattice_samples, (unsigned long long)lat);
+            atomicAdd(&P.stats->evaluated_samples, (unsigned long long)ev);
+            atomicAdd(&P.stats->shaded_samples, (unsigned long long)sh);
+            atomicAdd(&P.stats->rays_hit, (unsigned long long)hit);
+        }
+    }
+}
+
 }  // namespace rc

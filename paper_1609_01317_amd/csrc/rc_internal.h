@@ -59,6 +59,7 @@ struct RenderParams {
     double eye[3], f[3], r[3], u[3];
     double tan_half, aspect, ortho_half;
     int projection, W, H;
+    int tile_w;                 // tile width in pixels (tile height = 64 / tile_w)
     int tiles_x, n_tiles;
     // sampling box (world) and lattice
     double lo[3], hi[3];
@@ -102,6 +103,7 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
 // `prefix` (tf_len + 1 ints) as scratch.
 rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
                             int* prefix, hipStream_t st);
+void set_tiling(RenderParams& P, int tile_w);   // tile_w in {4, 8, 16, 32, 64}
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
 
 }  // namespace rc

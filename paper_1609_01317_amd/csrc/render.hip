@@ -66,7 +66,7 @@ rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uin
 }
 
 // ---------------------------------------------------------------- the kernel
-// Workgroup = one wave = an 8x8 pixel tile.  Workgroups are dealt to the 8
+// Workgroup = one wave = one pixel tile.  Workgroups are dealt to the 8
 // XCDs round-robin; the swizzle gives each XCD a contiguous band of tiles so
 // neighbouring rays share that XCD's L2.
 __device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
@@ -75,44 +75,9 @@ __device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
     return xcd < rem ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
 }
 
-__device__ __forceinline__ unsigned wave_sum(unsigned v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 template <typename VT, int OP>
 __global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
-    int tile = xcd_swizzle(blockIdx.x, gridDim.x);
-    int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
-    int lane = threadIdx.x;
-    int px = tx * 8 + (lane & 7), py = ty * 8 + (lane >> 3);
-    bool valid = px < P.W && py < P.H;
-    MarchOut M;
-    M.rgba = make_float4(0.f, 0.f, 0.f, 0.f);
-    M.k_last = -1;
-    M.T = 1.0f;
-    M.evaluated = M.shaded = 0;
-    Ray R;
-    R.K = -1;
-    if (valid) {
-        setup_ray(P, px, py, R);
-        if (R.K >= 0) march<VT, OP>(P, R, M);
-        long long pix = (long long)py * P.W + px;
-        P.out[pix] = M.rgba;
-        if (P.aux) P.aux[pix] = rc_aux{M.k_last, M.T};
-    }
-    if (P.stats) {
-        unsigned lat = wave_sum(R.K >= 0 ? (unsigned)(M.k_last + 1) : 0u);
-        unsigned ev = wave_sum(M.evaluated);
-        unsigned sh = wave_sum(M.shaded);
-        unsigned hit = wave_sum(R.K >= 0 ? 1u : 0u);
-        if (lane == 0) {
-            atomicAdd(&P.stats->lattice_samples, (unsigned long long)lat);
-            atomicAdd(&P.stats->evaluated_samples, (unsigned long long)ev);
-            atomicAdd(&P.stats->shaded_samples, (unsigned long long)sh);
-            atomicAdd(&P.stats->rays_hit, (unsigned long long)hit);
-        }
-    }
+    render_tile<VT, OP>(P, xcd_swizzle(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 template <typename VT>
@@ -236,6 +201,13 @@ rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const floa
     return RC_OK;
 }
 
+void set_tiling(RenderParams& P, int tile_w) {
+    int th = 64 / tile_w;
+    P.tile_w = tile_w;
+    P.tiles_x = (P.W + tile_w - 1) / tile_w;
+    P.n_tiles = P.tiles_x * ((P.H + th - 1) / th);
+}
+
 static double op_gain(int op) {
     if (op == RC_GRAD_CENTRAL) return 2.0;
     if (op == RC_GRAD_SOBEL3D) {
@@ -265,8 +237,7 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     P.projection = cam->projection;
     P.W = cam->width;
     P.H = cam->height;
-    P.tiles_x = (cam->width + 7) / 8;
-    P.n_tiles = P.tiles_x * ((cam->height + 7) / 8);
+    set_tiling(P, 8);
     sampling_box(v, opt, P.lo, P.hi);
     P.step = opt->step;
     for (int a = 0; a < 3; ++a) {

@@ -41,6 +41,8 @@ def test_struct_layouts_match_header():
     assert C.sizeof(rc.rc_shading) == 8 + 4 * 4 + 3 * 4 + 4
     assert C.sizeof(rc.rc_options) == 8 + 6 * 8 + 4 * 4
     assert C.sizeof(rc.rc_stats) == 32
+    assert C.sizeof(rc.rc_batch_item) == 256
+    assert C.sizeof(rc.rc_batch_config) == 16
 
 
 def _status(fn, *args):
@@ -81,3 +83,20 @@ def test_render_rejects_null_volume_on_host():
     st, _ = _status("rc_build_bricks", None, 8, None)
     assert st == rc.RC_E_INVALID
     rc._L().rc_destroy_volume(None)     # NULL is ignored
+
+
+def test_batch_rejects_bad_arguments_on_host():
+    out = C.c_void_p()
+    st, _ = _status("rc_batch_create", None, 1, None, None, C.byref(out))
+    assert st == rc.RC_E_INVALID
+    items = (rc.rc_batch_item * 1)()
+    st, msg = _status("rc_batch_create", items, 1, None, None, C.byref(out))
+    assert st == rc.RC_E_INVALID and "item 0" in msg
+    bad = rc.rc_batch_config(7, 1, 8, 1)
+    st, msg = _status("rc_batch_create", items, 1, C.byref(bad), None, C.byref(out))
+    assert st == rc.RC_E_INVALID and "tile_w" in msg
+    st, _ = _status("rc_batch_render", None, 0, None)
+    assert st == rc.RC_E_INVALID
+    st, _ = _status("rc_batch_autotune", items, 1, None, None, C.byref(rc.rc_batch_config()))
+    assert st == rc.RC_E_INVALID
+    rc._L().rc_batch_destroy(None)

@@ -1,0 +1,155 @@
+"""Batched persistent rendering vs one rc_render per item (the same arithmetic,
+so outputs must be bit-identical), hipGraph replay vs eager, the autotuner,
+and the full 64-volume workload."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1609_01317_amd as rc
+import workloads as W
+from tests.gpu_util import compare, gpu_volume, oracle_render, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _scenes():
+    out = []
+    specs = [
+        dict(seed=41, dims=(26, 21, 19), dtype=np.uint8, image=(37, 29), op="central"),
+        dict(seed=42, dims=(40, 17, 33), dtype=np.uint16, image=(64, 48), op="sobel3d",
+             ert=0.99, skip=True),
+        dict(seed=43, dims=(12, 30, 9), dtype=np.float32, image=(16, 40), op="zucker_hummel",
+             shading="none"),
+        dict(seed=44, dims=(33, 33, 33), dtype=np.uint8, image=(8, 8), op="sobel3d",
+             projection="ortho", skip=True),
+        dict(seed=45, dims=(50, 44, 20), dtype=np.uint16, image=(128, 96), op="central",
+             ert=0.95, skip=True),
+        dict(seed=46, dims=(9, 9, 9), dtype=np.uint8, image=(3, 130), op="zucker_hummel",
+             shading="paper_lambert"),
+    ]
+    for sp in specs:
+        sc = W.config_small(**sp)
+        if sc.shading["model"] == "paper_lambert":
+            sc.shading["light_is_point"] = True
+            sc.shading["light"] = (40.0, -30.0, 35.0)
+        out.append(sc)
+    return out
+
+
+def _items(scenes):
+    items = []
+    for sc in scenes:
+        cam = sc.cameras[0]
+        items.append({"vol": gpu_volume(sc), "camera": cam, "tf": to_dev(sc.tf),
+                      "shading": sc.shading, "options": sc.options,
+                      "out": torch.full((cam["height"], cam["width"], 4), -1.0, device="cuda"),
+                      "aux": rc.new_aux(cam)})
+    return items
+
+
+def _reference(items):
+    refs = []
+    for it in items:
+        aux = rc.new_aux(it["camera"])
+        img = rc.rc_render(it["vol"], it["camera"], it["tf"], it["shading"], it["options"],
+                           aux=aux)
+        refs.append((img.clone(), aux.clone()))
+    torch.cuda.synchronize()
+    return refs
+
+
+@pytest.mark.parametrize("cfg", [None, dict(tile_w=16, waves_per_wg=4, wg_per_cu=2, order=0),
+                                 dict(tile_w=4, waves_per_wg=2, wg_per_cu=1, order=1),
+                                 dict(tile_w=32, waves_per_wg=1, wg_per_cu=32, order=1)])
+def test_batch_equals_single_renders(cfg):
+    scenes = _scenes()
+    items = _items(scenes)
+    refs = _reference(items)
+    rc.rc_render_batch(items, cfg)
+    torch.cuda.synchronize()
+    for it, (img, aux) in zip(items, refs):
+        assert torch.equal(it["out"], img)
+        assert torch.equal(it["aux"], aux)
+    # and against the oracle for one item of each dtype
+    for k in (0, 1, 2):
+        r = oracle_render(scenes[k])
+        err, bad = compare(items[k]["out"].cpu().numpy(), r, scenes[k].options["ert_threshold"])
+        assert not bad.any(), err
+
+
+def test_graph_replay_matches_eager():
+    scenes = _scenes()
+    items = _items(scenes)
+    refs = _reference(items)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = rc.rc_batch_create(items, stream=s)
+        for rep in range(4):
+            for it in items:
+                it["out"].fill_(float(rep))           # eager work between replays
+            rc.rc_batch_render(b, use_graph=True, stream=s)
+            s.synchronize()
+            for it, (img, aux) in zip(items, refs):
+                assert torch.equal(it["out"], img), f"replay {rep}"
+            # unrelated eager render on the same stream between replays
+            rc.rc_render(items[0]["vol"], items[0]["camera"], items[0]["tf"],
+                         items[0]["shading"], items[0]["options"])
+            s.synchronize()
+        rc.rc_batch_render(b, use_graph=False, stream=s)
+        s.synchronize()
+        for it, (img, aux) in zip(items, refs):
+            assert torch.equal(it["out"], img)
+        rc.rc_batch_destroy(b)
+
+
+def test_autotune_and_cache(tmp_path):
+    items = _items(_scenes())
+    path = str(tmp_path / "tune.jsonl")
+    cfg = rc.rc_batch_autotune(items, path)
+    assert cfg["tile_w"] in (4, 8, 16, 32) and cfg["wg_per_cu"] >= 1
+    lines = open(path).read().strip().splitlines()
+    assert len(lines) == 1 and json.loads(lines[0])["tile_w"] == cfg["tile_w"]
+    cfg2 = rc.rc_batch_autotune(items, path)       # cache hit: no new line
+    assert cfg2 == cfg and len(open(path).read().strip().splitlines()) == 1
+    refs = _reference(items)
+    rc.rc_render_batch(items, cfg)
+    torch.cuda.synchronize()
+    for it, (img, _) in zip(items, refs):
+        assert torch.equal(it["out"], img)
+
+
+def test_batch_rejects_bad_item():
+    items = _items(_scenes()[:2])
+    items[1]["options"] = dict(items[1]["options"], step=-1.0)
+    with pytest.raises(rc.RCError) as e:
+        rc.rc_batch_create(items)
+    assert e.value.status == rc.RC_E_INVALID and "item 1" in str(e.value)
+
+
+def test_c4_sixty_four_volumes():
+    """The 64-volume workload: one persistent launch (graph-replayed) equals 64
+    sequential renders bit for bit; 4 items are also checked on sampled
+    pixels against the oracle."""
+    scenes = W.config_c4()
+    items = _items(scenes)
+    refs = _reference(items)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = rc.rc_batch_create(items, stream=s)
+        for _ in range(2):
+            rc.rc_batch_render(b, use_graph=True, stream=s)
+        s.synchronize()
+    for it, (img, aux) in zip(items, refs):
+        assert torch.equal(it["out"], img)
+    rng = np.random.default_rng(404)
+    for k in (0, 17, 40, 63):
+        sc = scenes[k]
+        cam = sc.cameras[0]
+        pix = rng.choice(cam["width"] * cam["height"], size=2000, replace=False)
+        r = oracle_render(sc, pixels=pix)
+        err, bad = compare(items[k]["out"].cpu().numpy().reshape(-1, 4)[pix], r,
+                           sc.options["ert_threshold"])
+        assert not bad.any(), (k, err)
