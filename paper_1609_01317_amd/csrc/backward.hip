@@ -43,7 +43,10 @@ __device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R, 
                                            BwdSample& S) {
     double pv[3];
     lattice_point(P, R, k, S.C, pv);
-    float v = sample_value<VT>(P, (const VT*)P.vox, S.C);
+    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
+    int ox[4], oy[4], oz[4];
+    src.offsets(S.C, ox, oy, oz);
+    float v = sample_value<VT>(src.base, ox, oy, oz, S.C);
     S.vn = (v - P.vmin) * P.inv_range;
     float uu = fminf(fmaxf(S.vn, 0.0f), 1.0f) * P.Mm1;
     S.i = min((int)uu, P.M - 1);

@@ -88,7 +88,9 @@ __global__ __launch_bounds__(256) void raycast_batch(const RenderParams* __restr
                                                      const int* __restrict__ tile_off,
                                                      const int* __restrict__ order, int n,
                                                      int total, int* __restrict__ counter) {
+    extern __shared__ __align__(16) unsigned char lds_all[];
     const int lane = threadIdx.x & 63;
+    unsigned char* lds = lds_all + (threadIdx.x >> 6) * kWaveLdsBytes;
     for (;;) {
         int w = 0;
         if (lane == 0) w = atomicAdd(counter, 1);
@@ -103,15 +105,15 @@ __global__ __launch_bounds__(256) void raycast_batch(const RenderParams* __restr
         int tile = w - tile_off[lo];
         const RenderParams& P = items[item];
         switch (kinds[item]) {
-            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL>(P, tile, lane); break;
-            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D>(P, tile, lane); break;
-            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane); break;
-            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL>(P, tile, lane); break;
-            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D>(P, tile, lane); break;
-            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane); break;
-            case 6: render_tile<float, RC_GRAD_CENTRAL>(P, tile, lane); break;
-            case 7: render_tile<float, RC_GRAD_SOBEL3D>(P, tile, lane); break;
-            default: render_tile<float, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane); break;
+            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL>(P, tile, lane, (uint8_t*)lds); break;
+            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D>(P, tile, lane, (uint8_t*)lds); break;
+            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane, (uint8_t*)lds); break;
+            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL>(P, tile, lane, (uint16_t*)lds); break;
+            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D>(P, tile, lane, (uint16_t*)lds); break;
+            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane, (uint16_t*)lds); break;
+            case 6: render_tile<float, RC_GRAD_CENTRAL>(P, tile, lane, (float*)lds); break;
+            case 7: render_tile<float, RC_GRAD_SOBEL3D>(P, tile, lane, (float*)lds); break;
+            default: render_tile<float, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane, (float*)lds); break;
         }
     }
 }
@@ -278,7 +280,8 @@ static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
         hipLaunchKernelGGL(batch_mask, dim3(g), dim3(256), 0, s, b->d_jobs, b->n_jobs,
                            b->total_bricks, b->d_prefix, b->d_mask);
     }
-    hipLaunchKernelGGL(raycast_batch, dim3(b->grid), dim3(64 * b->cfg.waves_per_wg), 0, s,
+    hipLaunchKernelGGL(raycast_batch, dim3(b->grid), dim3(64 * b->cfg.waves_per_wg),
+                       (size_t)kWaveLdsBytes * b->cfg.waves_per_wg, s,
                        b->d_items, b->d_kinds, b->d_tile_off, b->d_order, b->n, b->total_tiles,
                        b->d_counter);
     RC_HIP(hipGetLastError());

@@ -3,19 +3,55 @@
 // lookup table, shading and front-to-back compositing with early ray
 // termination and brick skipping.  Included by the forward and batched
 // kernels so that both run the same arithmetic.
+//
+// Execution model: one wave (64 lanes) renders one pixel tile, one ray per
+// lane.  The wave marches in chunks of ray parameter t shared by all its
+// lanes.  For each chunk it reduces the lanes' sample cells to one
+// axis-aligned voxel box, asks the brick grid (one brick per lane, a wave
+// ballot) whether any sample in the chunk can have non-zero opacity, and
+// if so stages the box -- the chunk's cells plus the one-voxel-low /
+// two-voxel-high apron the 3x3x3 stencils and the trilinear corners need --
+// in LDS with 16-byte Morton-group loads.  The samples then read their
+// 8-voxel cell and 64-voxel stencil neighbourhood from LDS.  A chunk whose
+// box does not fit falls back to per-lane gathers from the bricked volume;
+// both sources hold the same voxel values, so the arithmetic and the
+// result are identical.
 #pragma once
 
 #include "rc_internal.h"
 
 namespace rc {
 
-// Accumulator type of the integer stencils: exact int32 for u8/u16 voxels.
-template <typename T> struct Acc { using type = int; };
-template <> struct Acc<float> { using type = float; };
+constexpr int kWaveLdsBytes = 8192;     // LDS box budget per wave
 
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+// Orders this wave's LDS writes before its later LDS reads (all lanes of a
+// wave run in lockstep, so waiting for the wave's own LDS traffic suffices).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // ---------------------------------------------------------------- ray set-up
 // Camera ray through the centre of pixel (px, py) and its span inside the
@@ -85,22 +121,52 @@ __device__ __forceinline__ void lattice_point(const RenderParams& P, const Ray& 
     }
 }
 
-// ---------------------------------------------------------------- sampling
-// Trilinear interpolation as 7 lerps, x then y then z (Section 3.4, eq. 2),
-// voxel indices clamped to the grid.
+// ---------------------------------------------------------------- voxel sources
+// A source turns the footprint [c-1, c+2] of a cell, per axis, into element
+// offsets; the voxel at footprint position (i, j, k) is base[ox[i]+oy[j]+oz[k]].
+//  * GlobalSrc: the bricked volume, indices clamped to the grid.
+//  * LdsSrc: the chunk box staged in LDS, which already holds the clamped
+//    values, so offsets are plain strides (constant x steps -> immediate
+//    LDS offsets).
 template <typename VT>
-__device__ __forceinline__ float sample_value(const RenderParams& P, const VT* __restrict__ vox,
-                                              const Cell& C) {
-    int x0 = clampi(C.c[0], 0, P.nx - 1), x1 = clampi(C.c[0] + 1, 0, P.nx - 1);
-    int y0 = clampi(C.c[1], 0, P.ny - 1), y1 = clampi(C.c[1] + 1, 0, P.ny - 1);
-    int z0 = clampi(C.c[2], 0, P.nz - 1), z1 = clampi(C.c[2] + 1, 0, P.nz - 1);
-    int ox0 = off_x(x0), ox1 = off_x(x1);
-    int oy0 = off_y(y0, P.sy), oy1 = off_y(y1, P.sy);
-    int oz0 = off_z(z0, P.sz), oz1 = off_z(z1, P.sz);
-    float v000 = (float)vox[ox0 + oy0 + oz0], v100 = (float)vox[ox1 + oy0 + oz0];
-    float v010 = (float)vox[ox0 + oy1 + oz0], v110 = (float)vox[ox1 + oy1 + oz0];
-    float v001 = (float)vox[ox0 + oy0 + oz1], v101 = (float)vox[ox1 + oy0 + oz1];
-    float v011 = (float)vox[ox0 + oy1 + oz1], v111 = (float)vox[ox1 + oy1 + oz1];
+struct GlobalSrc {
+    const VT* __restrict__ base;
+    int nx, ny, nz, sy, sz;
+    __device__ __forceinline__ void offsets(const Cell& C, int ox[4], int oy[4], int oz[4]) const {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ox[i] = off_x(clampi(C.c[0] - 1 + i, 0, nx - 1));
+            oy[i] = off_y(clampi(C.c[1] - 1 + i, 0, ny - 1), sy);
+            oz[i] = off_z(clampi(C.c[2] - 1 + i, 0, nz - 1), sz);
+        }
+    }
+};
+
+template <typename VT>
+struct LdsSrc {
+    const VT* base;
+    int lo[3];          // box origin (voxel index, may be negative)
+    int bx, bxy;        // row and slab strides in elements
+    __device__ __forceinline__ void offsets(const Cell& C, int ox[4], int oy[4], int oz[4]) const {
+        int x0 = C.c[0] - 1 - lo[0], y0 = C.c[1] - 1 - lo[1], z0 = C.c[2] - 1 - lo[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ox[i] = x0 + i;
+            oy[i] = (y0 + i) * bx;
+            oz[i] = (z0 + i) * bxy;
+        }
+    }
+};
+
+// ---------------------------------------------------------------- sampling
+// Trilinear interpolation as 7 lerps, x then y then z (Section 3.4, eq. 2).
+template <typename VT>
+__device__ __forceinline__ float sample_value(const VT* base, const int ox[4], const int oy[4],
+                                              const int oz[4], const Cell& C) {
+    float v000 = (float)base[ox[1] + oy[1] + oz[1]], v100 = (float)base[ox[2] + oy[1] + oz[1]];
+    float v010 = (float)base[ox[1] + oy[2] + oz[1]], v110 = (float)base[ox[2] + oy[2] + oz[1]];
+    float v001 = (float)base[ox[1] + oy[1] + oz[2]], v101 = (float)base[ox[2] + oy[1] + oz[2]];
+    float v011 = (float)base[ox[1] + oy[2] + oz[2]], v111 = (float)base[ox[2] + oy[2] + oz[2]];
     float i1 = lerpf(v000, v100, C.fr[0]);
     float i2 = lerpf(v010, v110, C.fr[0]);
     float i3 = lerpf(v001, v101, C.fr[0]);
@@ -124,95 +190,108 @@ __device__ __forceinline__ float4 tf_lookup(const RenderParams& P, float v) {
 }
 
 // ---------------------------------------------------------------- gradients
-// Section 3.5.  Each tap of the operator is a trilinear sample at p + o;
-// by linearity that equals the trilinear blend of the integer stencil
-// evaluated at the 8 corners of the cell, which is what is computed here:
-// the 4x4x4 neighbourhood [c-1, c+2]^3 is gathered (each index clamped to
-// the grid), the stencil is applied at the 8 corners in exact integer
-// arithmetic for u8/u16 (float for f32 voxels and for the irrational
-// Zucker-Hummel weights), and the corner results are blended with the
-// same 7-lerp cascade as the value.
-//   CD      eq. (3): V(+1) - V(-1) along the axis
-//   Sobel3D eq. (4): +1 slice minus -1 slice, weights [[1,3,1],[3,6,3],[1,3,1]]
-//   ZH      weights 1/sqrt(1 + b^2 + c^2) on the same slices
 // Sobel3D smoothing weights of eq. (4): [[1,3,1],[3,6,3],[1,3,1]].
 __host__ __device__ constexpr int sobel_weight(int b, int e) {
     return (b == 0 && e == 0) ? 6 : (b == 0 || e == 0) ? 3 : 1;
 }
 
-template <typename VT, int OP>
-__device__ __forceinline__ void gradient(const RenderParams& P, const VT* __restrict__ vox,
-                                         const Cell& C, float g[3]) {
-    using A = typename Acc<VT>::type;
-    int ox[4], oy[4], oz[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        ox[i] = off_x(clampi(C.c[0] - 1 + i, 0, P.nx - 1));
-        oy[i] = off_y(clampi(C.c[1] - 1 + i, 0, P.ny - 1), P.sy);
-        oz[i] = off_z(clampi(C.c[2] - 1 + i, 0, P.nz - 1), P.sz);
-    }
-    A B[4][4][4];   // [z][y][x]; unused entries are never loaded (CD)
-#pragma unroll
-    for (int z = 0; z < 4; ++z)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int x = 0; x < 4; ++x) B[z][y][x] = (A)vox[ox[x] + oy[y] + oz[z]];
+// Section 3.5.  Each tap of the operator is a trilinear sample at p + o;
+// by linearity that equals the trilinear blend of the stencil evaluated at
+// the 8 corners of the cell:
+//   G_x = sum_c w_c sum_{b,e} W(b,e) [V(c + (1,b,e)) - V(c - (1,-b,-e))]
+// over the 4x4x4 neighbourhood [c-1, c+2]^3.  The 3x3 smoothing mask of
+// each operator is a separable product plus a centre correction,
+//   Sobel3D (eq. 4)  W = A (x) A - 3 delta,  A = [1, 3, 1]
+//   Zucker-Hummel    W = A (x) A + (1 - q^2/r) delta,  A = [sqrt r, q/sqrt r, sqrt r],
+//                    r = 1/sqrt 3 (corners), q = 1/sqrt 2 (edges), centre 1
+//   central diff.    W = delta (eq. 3)
+// and the corner weights w_c are separable too, so G is a sum of separable
+// 4x4x4 filters.  Their per-axis taps (corner weights folded in, t = the
+// cell fraction):
+//   L  = [0, 1-t, t, 0]                       (lerp)
+//   D' = [-(1-t), -t, 1-t, t]                 (lerp (x) the +-1 difference)
+//   A' = [a1(1-t), a0(1-t)+a1 t, a1(1-t)+a0 t, a1 t]   (lerp (x) A = [a1,a0,a1])
+// G_x = sum V D'x A'y A'z + gamma sum V D'x Ly Lz, cyclically for y and z.
+// The neighbourhood is streamed one z-slice (4x4 voxels) at a time.
+template <int OP> struct OpTaps;
+template <> struct OpTaps<RC_GRAD_CENTRAL> {
+    static constexpr bool kSep = false;
+    static constexpr float a0 = 0.f, a1 = 0.f, gamma = 1.0f;
+};
+template <> struct OpTaps<RC_GRAD_SOBEL3D> {
+    static constexpr bool kSep = true;
+    static constexpr float a0 = 3.0f, a1 = 1.0f, gamma = -3.0f;
+};
+template <> struct OpTaps<RC_GRAD_ZUCKER_HUMMEL> {
+    // a1 = sqrt(1/sqrt 3), a0 = (1/sqrt 2) / a1, gamma = 1 - a0^2
+    static constexpr bool kSep = true;
+    static constexpr float a1 = 0.75983568565159271f, a0 = 0.93060485910209953f,
+                           gamma = 0.13397459621556135f;
+};
 
-    float S[3][2][2][2];   // [component][cz][cy][cx]
+__device__ __forceinline__ float dot4(const float a[4], const float b[4]) {
+    return fmaf(a[3], b[3], fmaf(a[2], b[2], fmaf(a[1], b[1], a[0] * b[0])));
+}
+
+struct AxisTaps {
+    float L[4], D[4], A[4];
+};
+
+template <int OP>
+__device__ __forceinline__ void axis_taps(float t, AxisTaps& k) {
+    const float w0 = 1.0f - t, w1 = t;
+    k.L[0] = 0.f; k.L[1] = w0; k.L[2] = w1; k.L[3] = 0.f;
+    k.D[0] = -w0; k.D[1] = -w1; k.D[2] = w0; k.D[3] = w1;
+    const float a0 = OpTaps<OP>::a0, a1 = OpTaps<OP>::a1;
+    k.A[0] = a1 * w0;
+    k.A[1] = fmaf(a0, w0, a1 * w1);
+    k.A[2] = fmaf(a1, w0, a0 * w1);
+    k.A[3] = a1 * w1;
+}
+
+template <typename VT, int OP>
+__device__ __forceinline__ void gradient(const RenderParams& P, const VT* base, const int ox[4],
+                                         const int oy[4], const int oz[4], const Cell& C,
+                                         float g[3]) {
+    constexpr bool SEP = OpTaps<OP>::kSep;
+    AxisTaps kx, ky, kz;
+    axis_taps<OP>(C.fr[0], kx);
+    axis_taps<OP>(C.fr[1], ky);
+    axis_taps<OP>(C.fr[2], kz);
+    float gxA = 0.f, gyA = 0.f, gzA = 0.f, gxL = 0.f, gyL = 0.f, gzL = 0.f;
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
+    for (int z = 0; z < 4; ++z) {
+        float rowD[4], rowA[4], rowL[4];
 #pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
+        for (int y = 0; y < 4; ++y) {
+            float v[4];
 #pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                const int X = cx + 1, Y = cy + 1, Z = cz + 1;
-                if (OP == RC_GRAD_CENTRAL) {
-                    S[0][cz][cy][cx] = (float)(B[Z][Y][X + 1] - B[Z][Y][X - 1]);
-                    S[1][cz][cy][cx] = (float)(B[Z][Y + 1][X] - B[Z][Y - 1][X]);
-                    S[2][cz][cy][cx] = (float)(B[Z + 1][Y][X] - B[Z - 1][Y][X]);
-                } else if (OP == RC_GRAD_SOBEL3D) {
-                    A sx = 0, sy = 0, sz = 0;
-#pragma unroll
-                    for (int b = -1; b <= 1; ++b)
-#pragma unroll
-                        for (int e = -1; e <= 1; ++e) {
-                            const A w = (A)sobel_weight(b, e);
-                            sx += w * (B[Z + e][Y + b][X + 1] - B[Z + e][Y + b][X - 1]);
-                            sy += w * (B[Z + b][Y + 1][X + e] - B[Z + b][Y - 1][X + e]);
-                            sz += w * (B[Z + 1][Y + e][X + b] - B[Z - 1][Y + e][X + b]);
-                        }
-                    S[0][cz][cy][cx] = (float)sx;
-                    S[1][cz][cy][cx] = (float)sy;
-                    S[2][cz][cy][cx] = (float)sz;
-                } else {
-                    float sx = 0.f, sy = 0.f, sz = 0.f;
-#pragma unroll
-                    for (int b = -1; b <= 1; ++b)
-#pragma unroll
-                        for (int e = -1; e <= 1; ++e) {
-                            const int n2 = b * b + e * e;
-                            const float w = n2 == 0 ? 1.0f : n2 == 1 ? 0.70710678118654752f
-                                                                    : 0.57735026918962576f;
-                            sx = fmaf(w, (float)(B[Z + e][Y + b][X + 1] - B[Z + e][Y + b][X - 1]), sx);
-                            sy = fmaf(w, (float)(B[Z + b][Y + 1][X + e] - B[Z + b][Y - 1][X + e]), sy);
-                            sz = fmaf(w, (float)(B[Z + 1][Y + e][X + b] - B[Z - 1][Y + e][X + b]), sz);
-                        }
-                    S[0][cz][cy][cx] = sx;
-                    S[1][cz][cy][cx] = sy;
-                    S[2][cz][cy][cx] = sz;
-                }
-            }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float i1 = lerpf(S[a][0][0][0], S[a][0][0][1], C.fr[0]);
-        float i2 = lerpf(S[a][0][1][0], S[a][0][1][1], C.fr[0]);
-        float i3 = lerpf(S[a][1][0][0], S[a][1][0][1], C.fr[0]);
-        float i4 = lerpf(S[a][1][1][0], S[a][1][1][1], C.fr[0]);
-        float i5 = lerpf(i1, i2, C.fr[1]);
-        float i6 = lerpf(i3, i4, C.fr[1]);
-        g[a] = lerpf(i5, i6, C.fr[2]) * P.gscale[a];
+            for (int x = 0; x < 4; ++x) v[x] = (float)base[ox[x] + oy[y] + oz[z]];
+            rowD[y] = dot4(kx.D, v);
+            rowL[y] = fmaf(kx.L[2], v[2], kx.L[1] * v[1]);
+            rowA[y] = SEP ? dot4(kx.A, v) : 0.f;
+        }
+        const float xL = fmaf(ky.L[2], rowD[2], ky.L[1] * rowD[1]);
+        const float yL = dot4(ky.D, rowL);
+        const float zL = fmaf(ky.L[2], rowL[2], ky.L[1] * rowL[1]);
+        if (z == 1 || z == 2) {             // L vanishes on the outer slices
+            gxL = fmaf(kz.L[z], xL, gxL);
+            gyL = fmaf(kz.L[z], yL, gyL);
+        }
+        gzL = fmaf(kz.D[z], zL, gzL);
+        if (SEP) {
+            const float xA = dot4(ky.A, rowD);
+            const float yA = dot4(ky.D, rowA);
+            const float zA = dot4(ky.A, rowA);
+            gxA = fmaf(kz.A[z], xA, gxA);
+            gyA = fmaf(kz.A[z], yA, gyA);
+            gzA = fmaf(kz.D[z], zA, gzA);
+        }
     }
+    const float gm = OpTaps<OP>::gamma;
+    g[0] = fmaf(gm, gxL, gxA) * P.gscale[0];
+    g[1] = fmaf(gm, gyL, gyA) * P.gscale[1];
+    g[2] = fmaf(gm, gzL, gzA) * P.gscale[2];
 }
 
 // ---------------------------------------------------------------- shading
@@ -220,7 +299,7 @@ __device__ __forceinline__ void gradient(const RenderParams& P, const VT* __rest
 // N = -G/max(|G|, eps).  Alpha is never shaded.
 __device__ __forceinline__ void shade(const RenderParams& P, const float4& rgba, const float g[3],
                                       const double pv[3], const float dneg[3], float c[3]) {
-    float gl = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    float gl = sqrtf(fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0])));
     float inv = 1.0f / fmaxf(gl, P.grad_eps);
     float gh[3] = {g[0] * inv, g[1] * inv, g[2] * inv};
     float L[3];
@@ -253,43 +332,73 @@ __device__ __forceinline__ void shade(const RenderParams& P, const float4& rgba,
     c[2] = fmaf(rgba.z, k, P.ks * spec);
 }
 
-// ---------------------------------------------------------------- skipping
-// Brick of a cell: the brick holding the clamped cell index; every voxel a
-// sample in that cell reads lies inside the brick's recorded range.
-__device__ __forceinline__ int brick_of(const RenderParams& P, const Cell& C, int b[3]) {
-    b[0] = clampi(C.c[0], 0, P.nx - 1) >> 3;
-    b[1] = clampi(C.c[1], 0, P.ny - 1) >> 3;
-    b[2] = clampi(C.c[2], 0, P.nz - 1) >> 3;
-    return (b[2] * P.nby + b[1]) * P.nbx + b[0];
+// ---------------------------------------------------------------- LDS staging
+// Stage the voxel box [lo, lo + dim) (dims even, lo even) into LDS as
+// [z][y][x] elements.  Work unit: a 2x2x2 Morton group, which is 8
+// contiguous voxels in the bricked layout (one 16-byte load for u16) and 4
+// x-pairs of the LDS box.  Groups that reach outside the padded brick grid
+// (volume edges) are read voxel by voxel with clamped indices.
+template <typename VT> struct PairT;
+template <> struct PairT<uint8_t> { using type = uint16_t; };
+template <> struct PairT<uint16_t> { using type = uint32_t; };
+template <> struct PairT<float> { using type = uint2; };
+
+template <typename VT> struct GroupT;
+template <> struct GroupT<uint8_t> { using type = uint2; };
+template <> struct GroupT<uint16_t> { using type = uint4; };
+template <> struct GroupT<float> { struct type { uint4 a, b; }; };
+
+template <typename VT>
+__device__ __forceinline__ void group_pairs(const typename GroupT<VT>::type& g,
+                                            typename PairT<VT>::type p[4]);
+template <>
+__device__ __forceinline__ void group_pairs<uint8_t>(const uint2& g, uint16_t p[4]) {
+    p[0] = (uint16_t)(g.x & 0xffffu); p[1] = (uint16_t)(g.x >> 16);
+    p[2] = (uint16_t)(g.y & 0xffffu); p[3] = (uint16_t)(g.y >> 16);
+}
+template <>
+__device__ __forceinline__ void group_pairs<uint16_t>(const uint4& g, uint32_t p[4]) {
+    p[0] = g.x; p[1] = g.y; p[2] = g.z; p[3] = g.w;
+}
+template <>
+__device__ __forceinline__ void group_pairs<float>(const GroupT<float>::type& g, uint2 p[4]) {
+    p[0] = make_uint2(g.a.x, g.a.y); p[1] = make_uint2(g.a.z, g.a.w);
+    p[2] = make_uint2(g.b.x, g.b.y); p[3] = make_uint2(g.b.z, g.b.w);
 }
 
-// First lattice index that may lie outside brick b, rounded down so that no
-// sample outside the brick is ever skipped: along each axis the ray leaves
-// the brick through the plane 8(b+1) (moving up) or 8b (moving down); the
-// last/first brick extends to the end of the clamped range.
-__device__ inline long long brick_exit(const RenderParams& P, const Ray& R, const int b[3],
-                                       long long k) {
-    const int nb[3] = {P.nbx, P.nby, P.nbz};
-    double kmin = INFINITY;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double D = P.step * R.d[a] * P.inv_s[a];
-        double P0 = (R.o[a] + R.t_in * R.d[a]) * P.inv_s[a];
-        double plane;
-        if (D > 0.0) {
-            if (b[a] == nb[a] - 1) continue;
-            plane = 8.0 * (b[a] + 1);
-        } else if (D < 0.0) {
-            if (b[a] == 0) continue;
-            plane = 8.0 * b[a];
+template <typename VT>
+__device__ inline void stage_box(const RenderParams& P, VT* lds, const int lo[3], const int dim[3],
+                                 int lane) {
+    using G = typename GroupT<VT>::type;
+    using PT = typename PairT<VT>::type;
+    const VT* __restrict__ vox = (const VT*)P.vox;
+    const int gx = dim[0] >> 1, gy = dim[1] >> 1;
+    const int ng = gx * gy * (dim[2] >> 1);
+    const int xmax = P.nbx * 8, ymax = P.nby * 8, zmax = P.nbz * 8;
+    const int bx = dim[0], bxy = dim[0] * dim[1];
+    for (int g = lane; g < ng; g += 64) {
+        int ix = g % gx, r = g / gx;
+        int iy = r % gy, iz = r / gy;
+        int x0 = lo[0] + 2 * ix, y0 = lo[1] + 2 * iy, z0 = lo[2] + 2 * iz;
+        int l0 = (2 * iz * dim[1] + 2 * iy) * bx + 2 * ix;       // element offset of (x0,y0,z0)
+        if (x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + 1 < xmax && y0 + 1 < ymax && z0 + 1 < zmax) {
+            const G* src = (const G*)(vox + off_x(x0) + off_y(y0, P.sy) + off_z(z0, P.sz));
+            PT p[4];
+            group_pairs<VT>(*src, p);
+            *(PT*)(lds + l0) = p[0];
+            *(PT*)(lds + l0 + bx) = p[1];
+            *(PT*)(lds + l0 + bxy) = p[2];
+            *(PT*)(lds + l0 + bxy + bx) = p[3];
         } else {
-            continue;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+                int x = clampi(x0 + dx, 0, P.nx - 1), y = clampi(y0 + dy, 0, P.ny - 1),
+                    z = clampi(z0 + dz, 0, P.nz - 1);
+                lds[l0 + dz * bxy + dy * bx + dx] = vox[off_x(x) + off_y(y, P.sy) + off_z(z, P.sz)];
+            }
         }
-        kmin = fmin(kmin, (plane - P0) / D);
     }
-    if (!(kmin < 9.0e15)) return R.K + 1;
-    long long kn = (long long)floor(kmin);
-    return kn > k + 1 ? kn : k + 1;
 }
 
 // ---------------------------------------------------------------- the march
@@ -300,84 +409,223 @@ struct MarchOut {
     unsigned evaluated, shaded;
 };
 
-// Section 3.10: sampling -> shading -> compositing, front to back.  The
-// transparency formula of Section 3.9 (eq. 6, back to front) is evaluated
-// in its equivalent front-to-back form C += T a c, T *= (1 - a); the march
-// stops after the first sample with 1 - T >= tau (early ray termination).
+// Per-lane compositing state (Section 3.9, eq. 6 evaluated front to back:
+// C += T a c, T *= 1 - a; early termination after the first sample with
+// 1 - T >= tau).
+struct LaneState {
+    float Cr, Cg, Cb, T;
+    long long k;            // next lattice index
+    long long k_term;       // index where early termination fired, -1 if not
+    bool done;
+    unsigned evaluated, shaded;
+};
+
+// Chunk geometry shared by the wave.
+struct Chunk {
+    int lo[3], dim[3];          // LDS box
+    int blo[3], bdim[3];        // brick range of the samples' cells
+    unsigned long long live;    // bit set = brick may hold a non-zero-opacity sample
+    bool mask_valid;            // live covers every brick of the chunk
+};
+
+// One evaluated sample: value, table, and for non-zero opacity the
+// gradient, shading and compositing.  Returns true when the ray terminates.
+template <typename VT, int OP, typename Src>
+__device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& src, const Cell& C,
+                                             const double pv[3], const float dneg[3],
+                                             LaneState& S) {
+    int ox[4], oy[4], oz[4];
+    src.offsets(C, ox, oy, oz);
+    float v = sample_value<VT>(src.base, ox, oy, oz, C);
+    float4 rgba = tf_lookup(P, v);
+    float a = rgba.w;
+    if (a == 0.0f) return false;
+    ++S.shaded;
+    float c[3] = {rgba.x, rgba.y, rgba.z};
+    if (P.shade != RC_SHADE_NONE) {
+        float g[3];
+        gradient<VT, OP>(P, src.base, ox, oy, oz, C, g);
+        shade(P, rgba, g, pv, dneg, c);
+    }
+    float ta = S.T * a;
+    S.Cr = fmaf(ta, c[0], S.Cr);
+    S.Cg = fmaf(ta, c[1], S.Cg);
+    S.Cb = fmaf(ta, c[2], S.Cb);
+    S.T *= (1.0f - a);
+    return P.tau > 0.0f && 1.0f - S.T >= P.tau;
+}
+
+// Evaluate lattice samples S.k .. kstop of this lane's ray.  Samples in
+// bricks known to be empty are not evaluated (their opacity is exactly 0,
+// so they change nothing).  A sample reads the LDS box when `staged` and its
+// 4x4x4 footprint lies inside the box, else the bricked volume.
 template <typename VT, int OP>
-__device__ inline void march(const RenderParams& P, const Ray& R, MarchOut& M) {
-    const VT* __restrict__ vox = (const VT*)P.vox;
-    float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
-    const float dneg[3] = {(float)-R.d[0], (float)-R.d[1], (float)-R.d[2]};
-    unsigned evaluated = 0, shaded = 0;
-    long long k_last = R.K;
-    for (long long k = 0; k <= R.K;) {
+__device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
+                                            const LdsSrc<VT>& lsrc, const GlobalSrc<VT>& gsrc,
+                                            bool staged, const Chunk& ch, long long kstop,
+                                            const float dneg[3], LaneState& S) {
+    for (long long k = S.k; k <= kstop; ++k) {
         Cell C;
         double pv[3];
         lattice_point(P, R, k, C, pv);
         if (P.skip) {
-            int b[3];
-            int bi = brick_of(P, C, b);
-            if (P.empty[bi]) {
-                k = brick_exit(P, R, b, k);
+            int b0 = clampi(C.c[0], 0, P.nx - 1) >> 3, b1 = clampi(C.c[1], 0, P.ny - 1) >> 3,
+                b2 = clampi(C.c[2], 0, P.nz - 1) >> 3;
+            int r0 = b0 - ch.blo[0], r1 = b1 - ch.blo[1], r2 = b2 - ch.blo[2];
+            bool empty;
+            if (ch.mask_valid && r0 >= 0 && r1 >= 0 && r2 >= 0 && r0 < ch.bdim[0] &&
+                r1 < ch.bdim[1] && r2 < ch.bdim[2])
+                empty = ((ch.live >> ((r2 * ch.bdim[1] + r1) * ch.bdim[0] + r0)) & 1ull) == 0;
+            else
+                empty = P.empty[(b2 * P.nby + b1) * P.nbx + b0] != 0;
+            if (empty) continue;
+        }
+        ++S.evaluated;
+        bool in = staged;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            in = in && C.c[a] - 1 >= ch.lo[a] && C.c[a] + 2 < ch.lo[a] + ch.dim[a];
+        bool term = in ? shade_sample<VT, OP>(P, lsrc, C, pv, dneg, S)
+                       : shade_sample<VT, OP>(P, gsrc, C, pv, dneg, S);
+        if (term) {
+            S.k_term = k;
+            S.done = true;
+            return;
+        }
+    }
+}
+
+// Chunk lengths in lattice steps.
+constexpr int kChunkMin = 2, kChunkInit = 16, kChunkMax = 128;
+
+// March the 64 rays of this wave together.  `has_ray` is false for lanes
+// outside the image; they still take part in the wave-wide steps.
+template <typename VT, int OP>
+__device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_ray, VT* lds,
+                                  int lane, MarchOut& M) {
+    LaneState S;
+    S.Cr = S.Cg = S.Cb = 0.f;
+    S.T = 1.0f;
+    S.k = 0;
+    S.k_term = -1;
+    S.done = !has_ray || R.K < 0;
+    S.evaluated = S.shaded = 0;
+    const float dneg[3] = {(float)-R.d[0], (float)-R.d[1], (float)-R.d[2]};
+    const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
+    const int cap = kWaveLdsBytes / (int)sizeof(VT);
+    int len = kChunkInit;
+    for (;;) {
+        bool active = !S.done && S.k <= R.K;
+        if (!active) S.done = true;
+        if (__ballot(active) == 0ull) break;
+        // the chunk starts at the earliest pending sample of the wave
+        double tau = wave_min(active ? R.t_in + (double)S.k * P.step : INFINITY);
+        Chunk ch;
+        long long kstop = -1;
+        bool fits = false;
+        for (;;) {
+            double tau_end = tau + (double)len * P.step;
+            kstop = -1;
+            int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+            if (active) {
+                double q = ceil((tau_end - R.t_in) / P.step) - 1.0;
+                kstop = q < (double)R.K ? (long long)fmax(q, -1.0) : R.K;
+                // the lane(s) defining tau always own at least their next sample
+                if (R.t_in + (double)S.k * P.step < tau_end && kstop < S.k) kstop = S.k;
+                if (kstop >= S.k) {
+                    Cell c0, c1;
+                    double pv[3];
+                    lattice_point(P, R, S.k, c0, pv);
+                    lattice_point(P, R, kstop, c1, pv);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        mn[a] = min(c0.c[a], c1.c[a]);
+                        mx[a] = max(c0.c[a], c1.c[a]);
+                    }
+                }
+            }
+            int cmin[3], cmax[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cmin[a] = wave_min(mn[a]);
+                cmax[a] = wave_max(mx[a]);
+            }
+            if (cmin[0] > cmax[0]) {            // no lane has a sample before tau_end
+                fits = false;
+                ch.mask_valid = false;
+                for (int a = 0; a < 3; ++a) ch.lo[a] = ch.dim[a] = ch.blo[a] = ch.bdim[a] = 0;
+                break;
+            }
+            const int n[3] = {P.nx, P.ny, P.nz};
+            long long vol = 1;
+            int nbr = 1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ch.lo[a] = (cmin[a] - 1) & ~1;                    // even, one voxel of apron
+                ch.dim[a] = (((cmax[a] + 2) | 1) - ch.lo[a]) + 1;  // even, two voxels of apron
+                vol *= ch.dim[a];
+                ch.blo[a] = clampi(cmin[a], 0, n[a] - 1) >> 3;
+                ch.bdim[a] = (clampi(cmax[a], 0, n[a] - 1) >> 3) - ch.blo[a] + 1;
+                nbr *= ch.bdim[a];
+            }
+            fits = vol <= cap;
+            ch.mask_valid = nbr <= 64;
+            if ((fits && ch.mask_valid) || len <= kChunkMin) break;
+            len >>= 1;
+        }
+        // brick occupancy of the chunk: one brick per lane, one ballot
+        ch.live = ~0ull;
+        if (P.skip && ch.mask_valid) {
+            int nbr = ch.bdim[0] * ch.bdim[1] * ch.bdim[2];
+            bool live = false;
+            if (lane < nbr) {
+                int r0 = lane % ch.bdim[0], r1 = (lane / ch.bdim[0]) % ch.bdim[1],
+                    r2 = lane / (ch.bdim[0] * ch.bdim[1]);
+                int b = ((ch.blo[2] + r2) * P.nby + ch.blo[1] + r1) * P.nbx + ch.blo[0] + r0;
+                live = P.empty[b] == 0;
+            }
+            ch.live = __ballot(live);
+            if (ch.live == 0ull) {              // every sample of the chunk has alpha 0
+                if (active && kstop >= S.k) S.k = kstop + 1;
+                len = min(len * 2, kChunkMax);
                 continue;
             }
         }
-        ++evaluated;
-        float v = sample_value<VT>(P, vox, C);
-        float4 rgba = tf_lookup(P, v);
-        float a = rgba.w;
-        if (a != 0.0f) {
-            ++shaded;
-            float c[3] = {rgba.x, rgba.y, rgba.z};
-            if (P.shade != RC_SHADE_NONE) {
-                float g[3];
-                gradient<VT, OP>(P, vox, C, g);
-                shade(P, rgba, g, pv, dneg, c);
-            }
-            float ta = T * a;
-            Cr = fmaf(ta, c[0], Cr);
-            Cg = fmaf(ta, c[1], Cg);
-            Cb = fmaf(ta, c[2], Cb);
-            T *= (1.0f - a);
-            if (P.tau > 0.0f && 1.0f - T >= P.tau) {
-                k_last = k;
-                break;
-            }
+        if (fits) {
+            stage_box<VT>(P, lds, ch.lo, ch.dim, lane);
+            wave_lds_sync();
         }
-        ++k;
+        LdsSrc<VT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1]};
+        if (active && kstop >= S.k)
+            run_samples<VT, OP>(P, R, lsrc, gsrc, fits, ch, kstop, dneg, S);
+        if (fits) wave_lds_sync();
+        if (active && !S.done && kstop >= S.k) S.k = kstop + 1;
     }
-    M.rgba = make_float4(Cr, Cg, Cb, 1.0f - T);
-    M.k_last = (int)k_last;
-    M.T = T;
-    M.evaluated = evaluated;
-    M.shaded = shaded;
+    M.rgba = make_float4(S.Cr, S.Cg, S.Cb, 1.0f - S.T);
+    M.k_last = (int)(S.k_term >= 0 ? S.k_term : R.K);
+    M.T = S.T;
+    M.evaluated = S.evaluated;
+    M.shaded = S.shaded;
 }
 
 // ---------------------------------------------------------------- one tile
-__device__ __forceinline__ unsigned wave_sum(unsigned v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
 // One wave renders one tile of tile_w x (64 / tile_w) pixels; `tile` is the
-// tile's row-major index in the image.  Lanes outside the image idle.
+// tile's row-major index in the image.  Lanes outside the image take part
+// in the wave-wide steps without a ray.
 template <typename VT, int OP>
-__device__ inline void render_tile(const RenderParams& P, int tile, int lane) {
+__device__ inline void render_tile(const RenderParams& P, int tile, int lane, VT* lds) {
     const int tw = P.tile_w, th = 64 / P.tile_w;
     int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
     int px = tx * tw + (lane % tw), py = ty * th + (lane / tw);
     bool valid = px < P.W && py < P.H;
-    MarchOut M;
-    M.rgba = make_float4(0.f, 0.f, 0.f, 0.f);
-    M.k_last = -1;
-    M.T = 1.0f;
-    M.evaluated = M.shaded = 0;
     Ray R;
     R.K = -1;
+    R.t_in = 0.0;
+    for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = 0.0;
+    if (valid) setup_ray(P, px, py, R);
+    MarchOut M;
+    march_wave<VT, OP>(P, R, valid, lds, lane, M);
     if (valid) {
-        setup_ray(P, px, py, R);
-        if (R.K >= 0) march<VT, OP>(P, R, M);
         long long pix = (long long)py * P.W + px;
         P.out[pix] = M.rgba;
         if (P.aux) P.aux[pix] = rc_aux{M.k_last, M.T};

@@ -77,7 +77,8 @@ __device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
 
 template <typename VT, int OP>
 __global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
-    render_tile<VT, OP>(P, xcd_swizzle(blockIdx.x, gridDim.x), threadIdx.x);
+    __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
+    render_tile<VT, OP>(P, xcd_swizzle(blockIdx.x, gridDim.x), threadIdx.x, (VT*)lds);
 }
 
 template <typename VT>
