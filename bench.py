@@ -100,7 +100,7 @@ def run_c3(args):
     # untimed counting pass: lattice / evaluated / shaded samples per view
     counts = {}
     for op in OPS:
-        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        st = rc.new_stats()
         per_view = []
         for cam in sc.cameras:
             st.zero_()
@@ -167,7 +167,7 @@ def run_c5(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
-    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    st = rc.new_stats()
     for cam in sc.cameras:
         rc.rc_render(h, cam, tf0, sc.shading, sc.options, stats=st)
     lattice = int(st[0].item())
@@ -196,7 +196,7 @@ def run_c4(args):
         items.append({"vol": vol, "camera": cam, "tf": to_dev(sc.tf), "shading": sc.shading,
                       "options": sc.options,
                       "out": torch.empty((cam["height"], cam["width"], 4), device="cuda")})
-    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    st = rc.new_stats()
     for it in items:
         rc.rc_render(it["vol"], it["camera"], it["tf"], it["shading"], it["options"], stats=st)
     lattice = int(st[0].item())
@@ -304,7 +304,11 @@ def main():
                       "lattice_gsamples_s": round(lat / (ms * 1e-3) / 1e9, 3),
                       "evaluated_gsamples_s": round(ev / (ms * 1e-3) / 1e9, 3),
                       "lattice_samples": lat, "evaluated_samples": ev,
-                      "shaded_samples": int(counts[op][:, 2].sum())}
+                      "shaded_samples": int(counts[op][:, 2].sum()),
+                      "chunks_staged": int(counts[op][:, 4].sum()),
+                      "chunks_empty": int(counts[op][:, 5].sum()),
+                      "chunks_direct": int(counts[op][:, 6].sum()),
+                      "samples_direct": int(counts[op][:, 7].sum())}
     dom_op, roof = roofline(render_ms, counts)
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1,

@@ -103,6 +103,11 @@ typedef struct {
     unsigned long long evaluated_samples; /* lattice samples minus those skipped in empty bricks */
     unsigned long long shaded_samples;    /* samples with alpha != 0 */
     unsigned long long rays_hit;          /* rays that met the sampling box */
+    /* march diagnostics: a wave marches its rays in chunks of ray parameter */
+    unsigned long long chunks_staged;     /* chunks whose voxel box was staged in LDS */
+    unsigned long long chunks_empty;      /* chunks skipped: every brick they touch is empty */
+    unsigned long long chunks_direct;     /* chunks evaluated from the bricked volume directly */
+    unsigned long long samples_direct;    /* evaluated samples that read the bricked volume */
 } rc_stats;
 
 /* Per-pixel side output of a forward render, read by the reverse pass. */

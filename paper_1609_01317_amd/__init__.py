@@ -59,7 +59,17 @@ class rc_options(C.Structure):
 
 class rc_stats(C.Structure):
     _fields_ = [("lattice_samples", C.c_ulonglong), ("evaluated_samples", C.c_ulonglong),
-                ("shaded_samples", C.c_ulonglong), ("rays_hit", C.c_ulonglong)]
+                ("shaded_samples", C.c_ulonglong), ("rays_hit", C.c_ulonglong),
+                ("chunks_staged", C.c_ulonglong), ("chunks_empty", C.c_ulonglong),
+                ("chunks_direct", C.c_ulonglong), ("samples_direct", C.c_ulonglong)]
+
+
+STATS_FIELDS = [f for f, _ in rc_stats._fields_]
+
+
+def new_stats(device="cuda") -> torch.Tensor:
+    """Zeroed int64 tensor laid out as rc_stats (see STATS_FIELDS)."""
+    return torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device=device)
 
 
 class rc_batch_item(C.Structure):
@@ -240,7 +250,7 @@ def rc_render(vol: Volume, camera: dict, tf: torch.Tensor, shading: dict, option
 
     ``aux``: optional int64 [H,W] tensor receiving rc_aux records
     (k_last int32, t_final float32 packed per pixel).  ``stats``: optional
-    int64 [4] tensor accumulating rc_stats."""
+    int64 [8] tensor accumulating rc_stats (new_stats())."""
     _check_tf(tf)
     H, W = int(camera["height"]), int(camera["width"])
     if out is None:
@@ -249,8 +259,8 @@ def rc_render(vol: Volume, camera: dict, tf: torch.Tensor, shading: dict, option
         raise ValueError("out must be a contiguous float32 [H,W,4] tensor")
     if aux is not None and (aux.numel() != H * W or aux.element_size() * aux.numel() != 8 * H * W):
         raise ValueError("aux must hold H*W 8-byte records")
-    if stats is not None and stats.numel() * stats.element_size() != 32:
-        raise ValueError("stats must be 32 bytes (4 counters)")
+    if stats is not None and stats.numel() * stats.element_size() != C.sizeof(rc_stats):
+        raise ValueError(f"stats must be {C.sizeof(rc_stats)} bytes (rc_stats)")
     cam, sh, opt = camera_struct(camera), shading_struct(shading), options_struct(options)
     _check(_L().rc_render(vol.handle, C.byref(cam), _ptr(tf), tf.shape[0], C.byref(sh),
                           C.byref(opt), _ptr(out), _ptr(aux), _ptr(stats), _stream(stream)))

@@ -407,6 +407,8 @@ struct MarchOut {
     int k_last;
     float T;
     unsigned evaluated, shaded;
+    unsigned samples_direct;                        // per lane
+    unsigned chunks_staged, chunks_empty, chunks_direct;  // per wave (uniform)
 };
 
 // Per-lane compositing state (Section 3.9, eq. 6 evaluated front to back:
@@ -417,7 +419,7 @@ struct LaneState {
     long long k;            // next lattice index
     long long k_term;       // index where early termination fired, -1 if not
     bool done;
-    unsigned evaluated, shaded;
+    unsigned evaluated, shaded, direct;
 };
 
 // Chunk geometry shared by the wave.
@@ -485,6 +487,7 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             in = in && C.c[a] - 1 >= ch.lo[a] && C.c[a] + 2 < ch.lo[a] + ch.dim[a];
+        S.direct += in ? 0u : 1u;
         bool term = in ? shade_sample<VT, OP>(P, lsrc, C, pv, dneg, S)
                        : shade_sample<VT, OP>(P, gsrc, C, pv, dneg, S);
         if (term) {
@@ -509,7 +512,11 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     S.k = 0;
     S.k_term = -1;
     S.done = !has_ray || R.K < 0;
-    S.evaluated = S.shaded = 0;
+    S.evaluated = S.shaded = S.direct = 0;
+    unsigned n_staged = 0, n_empty = 0, n_direct = 0;
+    // Staging pays off when samples need the stencil neighbourhood; an
+    // unshaded march reads 8 voxels per sample and gathers them directly.
+    const bool stage = P.shade != RC_SHADE_NONE;
     const float dneg[3] = {(float)-R.d[0], (float)-R.d[1], (float)-R.d[2]};
     const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
     const int cap = kWaveLdsBytes / (int)sizeof(VT);
@@ -568,9 +575,9 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
                 ch.bdim[a] = (clampi(cmax[a], 0, n[a] - 1) >> 3) - ch.blo[a] + 1;
                 nbr *= ch.bdim[a];
             }
-            fits = vol <= cap;
+            fits = stage && vol <= cap;
             ch.mask_valid = nbr <= 64;
-            if ((fits && ch.mask_valid) || len <= kChunkMin) break;
+            if (((fits || !stage) && ch.mask_valid) || len <= kChunkMin) break;
             len >>= 1;
         }
         // brick occupancy of the chunk: one brick per lane, one ballot
@@ -586,14 +593,18 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
             }
             ch.live = __ballot(live);
             if (ch.live == 0ull) {              // every sample of the chunk has alpha 0
+                ++n_empty;
                 if (active && kstop >= S.k) S.k = kstop + 1;
                 len = min(len * 2, kChunkMax);
                 continue;
             }
         }
         if (fits) {
+            ++n_staged;
             stage_box<VT>(P, lds, ch.lo, ch.dim, lane);
             wave_lds_sync();
+        } else {
+            ++n_direct;
         }
         LdsSrc<VT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1]};
         if (active && kstop >= S.k)
@@ -606,6 +617,10 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     M.T = S.T;
     M.evaluated = S.evaluated;
     M.shaded = S.shaded;
+    M.samples_direct = S.direct;
+    M.chunks_staged = n_staged;
+    M.chunks_empty = n_empty;
+    M.chunks_direct = n_direct;
 }
 
 // ---------------------------------------------------------------- one tile
@@ -635,11 +650,16 @@ __device__ inline void render_tile(const RenderParams& P, int tile, int lane, VT
         unsigned ev = wave_sum(M.evaluated);
         unsigned sh = wave_sum(M.shaded);
         unsigned hit = wave_sum(R.K >= 0 ? 1u : 0u);
+        unsigned dir = wave_sum(M.samples_direct);
         if (lane == 0) {
             atomicAdd(&P.stats->lattice_samples, (unsigned long long)lat);
             atomicAdd(&P.stats->evaluated_samples, (unsigned long long)ev);
             atomicAdd(&P.stats->shaded_samples, (unsigned long long)sh);
             atomicAdd(&P.stats->rays_hit, (unsigned long long)hit);
+            atomicAdd(&P.stats->chunks_staged, (unsigned long long)M.chunks_staged);
+            atomicAdd(&P.stats->chunks_empty, (unsigned long long)M.chunks_empty);
+            atomicAdd(&P.stats->chunks_direct, (unsigned long long)M.chunks_direct);
+            atomicAdd(&P.stats->samples_direct, (unsigned long long)dir);
         }
     }
 }

@@ -66,24 +66,39 @@ rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uin
 }
 
 // ---------------------------------------------------------------- the kernel
-// Workgroup = one wave = one pixel tile.  Workgroups are dealt to the 8
-// XCDs round-robin; the swizzle gives each XCD a contiguous band of tiles so
-// neighbouring rays share that XCD's L2.
-__device__ __forceinline__ int xcd_swizzle(int bid, int nb) {
-    int q = nb / 8, rem = nb % 8;
-    int xcd = bid % 8, loc = bid / 8;
-    return xcd < rem ? xcd * (q + 1) + loc : rem * (q + 1) + (xcd - rem) * q + loc;
+// Workgroup = one wave = one pixel tile.  Workgroups are dealt to the 8 XCDs
+// round-robin by block index.  Tiles are grouped 4x4 (32x32 pixels) and the
+// groups are dealt round-robin to the XCDs: neighbouring tiles of a group
+// share one XCD's L2, and every XCD gets groups from all over the image, so
+// the dense middle of a volume is not left to one or two XCDs.
+constexpr int kGroupTiles = 4;
+
+__host__ __device__ inline int group_grid_blocks(int tiles_x, int tiles_y) {
+    int gx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
+    int gy = (tiles_y + kGroupTiles - 1) / kGroupTiles;
+    return ((gx * gy + 7) / 8) * 8 * kGroupTiles * kGroupTiles;
+}
+
+__device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
+    const int per = kGroupTiles * kGroupTiles;
+    int gx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
+    int xcd = b & 7, q = b >> 3;
+    int g = (q / per) * 8 + xcd, pos = q % per;
+    int tx = (g % gx) * kGroupTiles + pos % kGroupTiles;
+    int ty = (g / gx) * kGroupTiles + pos / kGroupTiles;
+    return (tx < tiles_x && ty < tiles_y) ? ty * tiles_x + tx : -1;
 }
 
 template <typename VT, int OP>
 __global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
     __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
-    render_tile<VT, OP>(P, xcd_swizzle(blockIdx.x, gridDim.x), threadIdx.x, (VT*)lds);
+    int tile = tile_of_block(blockIdx.x, P.tiles_x, P.n_tiles / P.tiles_x);
+    if (tile >= 0) render_tile<VT, OP>(P, tile, threadIdx.x, (VT*)lds);
 }
 
 template <typename VT>
 static void launch_fwd_t(const RenderParams& P, int op, hipStream_t st) {
-    dim3 grid((unsigned)P.n_tiles), block(64);
+    dim3 grid((unsigned)group_grid_blocks(P.tiles_x, P.n_tiles / P.tiles_x)), block(64);
     if (op == RC_GRAD_CENTRAL)
         hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_CENTRAL>), grid, block, 0, st, P);
     else if (op == RC_GRAD_SOBEL3D)

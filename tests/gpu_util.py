@@ -32,7 +32,7 @@ def gpu_render(sc, cam=None, vol=None, options=None, shading=None, stats=False):
     vol = vol or gpu_volume(sc, bricks=options["skip_empty"])
     tf = to_dev(sc.tf)
     aux = rc.new_aux(cam)
-    st = torch.zeros(4, dtype=torch.int64, device="cuda") if stats else None
+    st = rc.new_stats() if stats else None
     out = rc.rc_render(vol, cam, tf, shading, options, aux=aux, stats=st)
     torch.cuda.synchronize()
     k_last, t_final = rc.aux_fields(aux)

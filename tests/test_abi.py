@@ -40,7 +40,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(rc.rc_camera) == 16 + 11 * 8
     assert C.sizeof(rc.rc_shading) == 8 + 4 * 4 + 3 * 4 + 4
     assert C.sizeof(rc.rc_options) == 8 + 6 * 8 + 4 * 4
-    assert C.sizeof(rc.rc_stats) == 32
+    assert C.sizeof(rc.rc_stats) == 64
     assert C.sizeof(rc.rc_batch_item) == 256
     assert C.sizeof(rc.rc_batch_config) == 16
 
