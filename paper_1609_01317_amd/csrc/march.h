@@ -18,6 +18,8 @@
 // result are identical.
 #pragma once
 
+#include <climits>
+
 #include "rc_internal.h"
 
 namespace rc {
@@ -29,14 +31,23 @@ __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // ---------------------------------------------------------------- wave helpers
-__device__ __forceinline__ int wave_min(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return __builtin_amdgcn_readfirstlane(v);
+// Wave-wide min / max through DPP lane moves (quad permutes, row mirrors,
+// row broadcasts 15 and 31): the total lands in lane 63 and is read back as
+// a wave-uniform scalar.
+template <typename Op>
+__device__ __forceinline__ int wave_reduce_dpp(int v, int ident, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(ident, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
-__device__ __forceinline__ int wave_max(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return __builtin_amdgcn_readfirstlane(v);
-}
+struct MinOp { __device__ int operator()(int a, int b) const { return min(a, b); } };
+struct MaxOp { __device__ int operator()(int a, int b) const { return max(a, b); } };
+__device__ __forceinline__ int wave_min(int v) { return wave_reduce_dpp(v, INT_MAX, MinOp()); }
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce_dpp(v, INT_MIN, MaxOp()); }
 __device__ __forceinline__ double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
     return v;
@@ -372,30 +383,36 @@ __device__ inline void stage_box(const RenderParams& P, VT* lds, const int lo[3]
     using G = typename GroupT<VT>::type;
     using PT = typename PairT<VT>::type;
     const VT* __restrict__ vox = (const VT*)P.vox;
-    const int gx = dim[0] >> 1, gy = dim[1] >> 1;
-    const int ng = gx * gy * (dim[2] >> 1);
+    const int gx = dim[0] >> 1, gy = dim[1] >> 1, gz = dim[2] >> 1;
+    const int ncol = gx * gy;
     const int xmax = P.nbx * 8, ymax = P.nby * 8, zmax = P.nbz * 8;
     const int bx = dim[0], bxy = dim[0] * dim[1];
-    for (int g = lane; g < ng; g += 64) {
-        int ix = g % gx, r = g / gx;
-        int iy = r % gy, iz = r / gy;
-        int x0 = lo[0] + 2 * ix, y0 = lo[1] + 2 * iy, z0 = lo[2] + 2 * iz;
-        int l0 = (2 * iz * dim[1] + 2 * iy) * bx + 2 * ix;       // element offset of (x0,y0,z0)
-        if (x0 >= 0 && y0 >= 0 && z0 >= 0 && x0 + 1 < xmax && y0 + 1 < ymax && z0 + 1 < zmax) {
-            const G* src = (const G*)(vox + off_x(x0) + off_y(y0, P.sy) + off_z(z0, P.sz));
-            PT p[4];
-            group_pairs<VT>(*src, p);
-            *(PT*)(lds + l0) = p[0];
-            *(PT*)(lds + l0 + bx) = p[1];
-            *(PT*)(lds + l0 + bxy) = p[2];
-            *(PT*)(lds + l0 + bxy + bx) = p[3];
-        } else {
+    // each lane owns (x, y) columns of groups and walks them along z
+    for (int col = lane; col < ncol; col += 64) {
+        int ix = col % gx, iy = col / gx;
+        int x0 = lo[0] + 2 * ix, y0 = lo[1] + 2 * iy;
+        bool xy_in = x0 >= 0 && y0 >= 0 && x0 + 1 < xmax && y0 + 1 < ymax;
+        int oxy = xy_in ? off_x(x0) + off_y(y0, P.sy) : 0;
+        int l0 = 2 * iy * bx + 2 * ix;
+        for (int iz = 0; iz < gz; ++iz, l0 += 2 * bxy) {
+            int z0 = lo[2] + 2 * iz;
+            if (xy_in && z0 >= 0 && z0 + 1 < zmax) {
+                const G* src = (const G*)(vox + oxy + off_z(z0, P.sz));
+                PT p[4];
+                group_pairs<VT>(*src, p);
+                *(PT*)(lds + l0) = p[0];
+                *(PT*)(lds + l0 + bx) = p[1];
+                *(PT*)(lds + l0 + bxy) = p[2];
+                *(PT*)(lds + l0 + bxy + bx) = p[3];
+            } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
-                int x = clampi(x0 + dx, 0, P.nx - 1), y = clampi(y0 + dy, 0, P.ny - 1),
-                    z = clampi(z0 + dz, 0, P.nz - 1);
-                lds[l0 + dz * bxy + dy * bx + dx] = vox[off_x(x) + off_y(y, P.sy) + off_z(z, P.sz)];
+                for (int q = 0; q < 8; ++q) {
+                    int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+                    int x = clampi(x0 + dx, 0, P.nx - 1), y = clampi(y0 + dy, 0, P.ny - 1),
+                        z = clampi(z0 + dz, 0, P.nz - 1);
+                    lds[l0 + dz * bxy + dy * bx + dx] =
+                        vox[off_x(x) + off_y(y, P.sy) + off_z(z, P.sz)];
+                }
             }
         }
     }
