@@ -18,8 +18,11 @@ roofline position, and the FP64 CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -45,6 +48,34 @@ VOXELS_VALUE = 8
 VOXELS_SHADED = {"central": 32, "sobel3d": 64, "zucker_hummel": 64}
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "raycast_fwd_c3_orbit.txt")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources and the C header: HBM counters recorded in
+    the profile summary describe these sources only."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1609_01317_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "rc.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(op: str):
+    """HBM bytes per launch of raycast_fwd<uint16, op> from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
+    sources changed since the counters were taken."""
+    if not os.path.exists(PROFILE):
+        return None
+    text = open(PROFILE).read()
+    m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"hbm_bytes_per_launch\s+" + re.escape(op) + r":\s*([0-9.eE+]+)", text)
+    return float(m.group(1)) if m else None
 
 
 def log(*a):
@@ -121,7 +152,8 @@ def roofline(render_ms, counts):
     achieved = float(flops.mean()) / (avg_ms * 1e-3) / 1e12
     return op, {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+        "traffic": recorded_traffic(op),
         "kernel": f"raycast_fwd<uint16, {op}>", "avg_launch_ms": round(avg_ms, 4),
         "algorithmic_flops_per_launch": float(flops.mean()),
         "algorithmic_voxel_bytes_per_launch": float(

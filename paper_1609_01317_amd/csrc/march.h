@@ -25,6 +25,7 @@
 namespace rc {
 
 constexpr int kWaveLdsBytes = 8192;     // LDS box budget per wave
+constexpr int kStatSlots = 64;          // per-render counter copies (see render_tile)
 
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
 
@@ -669,14 +670,16 @@ __device__ inline void render_tile(const RenderParams& P, int tile, int lane, VT
         unsigned hit = wave_sum(R.K >= 0 ? 1u : 0u);
         unsigned dir = wave_sum(M.samples_direct);
         if (lane == 0) {
-            atomicAdd(&P.stats->lattice_samples, (unsigned long long)lat);
-            atomicAdd(&P.stats->evaluated_samples, (unsigned long long)ev);
-            atomicAdd(&P.stats->shaded_samples, (unsigned long long)sh);
-            atomicAdd(&P.stats->rays_hit, (unsigned long long)hit);
-            atomicAdd(&P.stats->chunks_staged, (unsigned long long)M.chunks_staged);
-            atomicAdd(&P.stats->chunks_empty, (unsigned long long)M.chunks_empty);
-            atomicAdd(&P.stats->chunks_direct, (unsigned long long)M.chunks_direct);
-            atomicAdd(&P.stats->samples_direct, (unsigned long long)dir);
+            // one of kStatSlots copies, so waves do not all hit one address
+            rc_stats* st = P.stats + (tile & (kStatSlots - 1));
+            atomicAdd(&st->lattice_samples, (unsigned long long)lat);
+            atomicAdd(&st->evaluated_samples, (unsigned long long)ev);
+            atomicAdd(&st->shaded_samples, (unsigned long long)sh);
+            atomicAdd(&st->rays_hit, (unsigned long long)hit);
+            atomicAdd(&st->chunks_staged, (unsigned long long)M.chunks_staged);
+            atomicAdd(&st->chunks_empty, (unsigned long long)M.chunks_empty);
+            atomicAdd(&st->chunks_direct, (unsigned long long)M.chunks_direct);
+            atomicAdd(&st->samples_direct, (unsigned long long)dir);
         }
     }
 }

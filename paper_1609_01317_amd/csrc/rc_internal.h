@@ -91,7 +91,7 @@ struct RenderParams {
     // outputs
     float4* out;
     rc_aux* aux;
-    rc_stats* stats;
+    rc_stats* stats;            // kStatSlots consecutive copies, or null
 };
 
 // Host-side preparation shared by the forward, reverse and batch paths.

@@ -96,6 +96,24 @@ __global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
     if (tile >= 0) render_tile<VT, OP>(P, tile, threadIdx.x, (VT*)lds);
 }
 
+// ---------------------------------------------------------------- counters
+// The render kernel spreads its counters over kStatSlots copies; these two
+// kernels clear the copies and fold them into the caller's rc_stats.
+constexpr int kStatWords = (int)(sizeof(rc_stats) / sizeof(unsigned long long));
+
+__global__ void stats_clear(unsigned long long* slots) {
+    for (int i = threadIdx.x; i < kStatSlots * kStatWords; i += blockDim.x) slots[i] = 0ull;
+}
+
+__global__ void stats_fold(const unsigned long long* __restrict__ slots,
+                           unsigned long long* __restrict__ out) {
+    int w = threadIdx.x;
+    if (w >= kStatWords) return;
+    unsigned long long acc = 0ull;
+    for (int s = 0; s < kStatSlots; ++s) acc += slots[s * kStatWords + w];
+    out[w] += acc;
+}
+
 template <typename VT>
 static void launch_fwd_t(const RenderParams& P, int op, hipStream_t st) {
     dim3 grid((unsigned)group_grid_blocks(P.tiles_x, P.n_tiles / P.tiles_x)), block(64);
@@ -308,18 +326,33 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
     fill_render_params(P, v, cam, tf_rgba_dev, tf_len, sh, opt);
     P.out = (float4*)out_rgba_dev;
     P.aux = aux_dev;
-    P.stats = stats_dev;
+    // per-render scratch: counter slots, empty mask, table prefix counts
+    const size_t stat_bytes = stats_dev ? sizeof(rc_stats) * kStatSlots : 0;
+    const size_t mask_bytes = opt->skip_empty ? (((size_t)v->nbricks + 255) & ~(size_t)255) : 0;
+    const size_t prefix_bytes = opt->skip_empty ? sizeof(int) * ((size_t)tf_len + 1) : 0;
     void* scratch = nullptr;
-    if (opt->skip_empty) {
-        size_t mask_bytes = ((size_t)v->nbricks + 255) & ~(size_t)255;
-        RC_HIP(hipMallocAsync(&scratch, mask_bytes + sizeof(int) * ((size_t)tf_len + 1), s));
-        uint8_t* mask = (uint8_t*)scratch;
-        int* prefix = (int*)((char*)scratch + mask_bytes);
+    if (stat_bytes + mask_bytes + prefix_bytes > 0)
+        RC_HIP(hipMallocAsync(&scratch, stat_bytes + mask_bytes + prefix_bytes, s));
+    char* sp = (char*)scratch;
+    if (stats_dev) {
+        P.stats = (rc_stats*)sp;
+        hipLaunchKernelGGL(stats_clear, dim3(1), dim3(256), 0, s, (unsigned long long*)sp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = hip_fail(e, "stats_clear");
+    }
+    if (st == RC_OK && opt->skip_empty) {
+        uint8_t* mask = (uint8_t*)(sp + stat_bytes);
+        int* prefix = (int*)(sp + stat_bytes + mask_bytes);
         st = launch_empty_mask(v, tf_rgba_dev, tf_len, mask, prefix, s);
-        if (st != RC_OK) { (void)hipFreeAsync(scratch, s); return st; }
         P.empty = mask;
     }
-    st = launch_forward(P, v->dtype, opt->gradient_op, s);
+    if (st == RC_OK) st = launch_forward(P, v->dtype, opt->gradient_op, s);
+    if (st == RC_OK && stats_dev) {
+        hipLaunchKernelGGL(stats_fold, dim3(1), dim3(64), 0, s, (const unsigned long long*)sp,
+                           (unsigned long long*)stats_dev);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = hip_fail(e, "stats_fold");
+    }
     if (scratch) {
         hipError_t e = hipFreeAsync(scratch, s);
         if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
