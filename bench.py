@@ -199,12 +199,23 @@ def run_c5(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
+    auxes = [rc.new_aux(cam) for cam in sc.cameras]
+    grads = [torch.randn((cam["height"], cam["width"], 4), device="cuda") for cam in sc.cameras]
+    gv = torch.zeros_like(vol_t)
+    gt = torch.zeros_like(tf0)
+
+    def bwd_only():
+        for cam, aux, g in zip(sc.cameras, auxes, grads):
+            rc.rc_render_backward(h, cam, tf0, sc.shading, sc.options, aux, g, gv, gt)
+
     st = rc.new_stats()
-    for cam in sc.cameras:
-        rc.rc_render(h, cam, tf0, sc.shading, sc.options, stats=st)
+    rc.rc_update_volume(h, vol_t)
+    for cam, aux in zip(sc.cameras, auxes):
+        rc.rc_render(h, cam, tf0, sc.shading, sc.options, aux=aux, stats=st)
     lattice = int(st[0].item())
     ms_f = timeit(fwd_only, args.c5_iters)
     ms_fb = timeit(fwd_bwd, args.c5_iters)
+    ms_b = timeit(bwd_only, args.c5_iters)
     return {
         "workload": "128^3 f32 blobs, learnable 256-entry TF, 16 views 256^2, step 0.5, unshaded, "
                     "L2 loss vs seed-55 target",
@@ -213,6 +224,7 @@ def run_c5(args):
         "fwd_gsamples_s": round(lattice / ms_f / 1e6, 3),
         "fwd_bwd_gsamples_s": round(lattice / ms_fb / 1e6, 3),
         "fwd_bwd_over_fwd_time": round(ms_fb / ms_f, 2),
+        "bwd_kernels_ms": round(ms_b, 3),
     }
 
 
@@ -312,6 +324,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the differentiable form")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB copy first")
+    ap.add_argument("--only", choices=["c4", "c5"], default=None,
+                    help="run only the batched (c4) or differentiable (c5) form and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -323,6 +337,9 @@ def main():
     torch.cuda.set_device(0)
     if args.calib_copy:
         calib_copy()
+    if args.only:
+        print(json.dumps(run_c4(args) if args.only == "c4" else run_c5(args)), flush=True)
+        return
 
     sc, vol, tf, ms_per_step, render_ms, counts = run_c3(args)
     lattice_step = int(sum(counts[op][:, 0].sum() for op in OPS))

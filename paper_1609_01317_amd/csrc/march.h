@@ -307,41 +307,68 @@ __device__ __forceinline__ void gradient(const RenderParams& P, const VT* base, 
 }
 
 // ---------------------------------------------------------------- shading
+// Per-ray shading constants: the view vector V = -d and, for a directional
+// light, the Blinn-Phong half vector H = normalize(L + V), which is the same
+// for every sample of the ray.
+struct RayShade {
+    float v[3];
+    float h[3];
+};
+
+__device__ __forceinline__ float rsq_or_zero(float x) {
+    return x > 0.0f ? __builtin_amdgcn_rsqf(x) : 0.0f;
+}
+
+__device__ __forceinline__ void ray_shade(const RenderParams& P, const Ray& R, RayShade& rs) {
+    rs.v[0] = (float)-R.d[0];
+    rs.v[1] = (float)-R.d[1];
+    rs.v[2] = (float)-R.d[2];
+    float h[3] = {P.light[0] + rs.v[0], P.light[1] + rs.v[1], P.light[2] + rs.v[2]};
+    float hi = rsq_or_zero(fmaf(h[2], h[2], fmaf(h[1], h[1], h[0] * h[0])));
+    rs.h[0] = h[0] * hi; rs.h[1] = h[1] * hi; rs.h[2] = h[2] * hi;
+}
+
 // Section 3.8.  G points towards larger values; the outward normal is
-// N = -G/max(|G|, eps).  Alpha is never shaded.
+// N = -G/max(|G|, eps).  Alpha is never shaded.  Hardware rsq / log2 / exp2
+// (about 1 ulp) stand in for the library normalise and pow.
 __device__ __forceinline__ void shade(const RenderParams& P, const float4& rgba, const float g[3],
-                                      const double pv[3], const float dneg[3], float c[3]) {
-    float gl = sqrtf(fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0])));
-    float inv = 1.0f / fmaxf(gl, P.grad_eps);
+                                      const double pv[3], const RayShade& rs, float c[3]) {
+    float g2 = fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
+    // 1 / max(|G|, eps) = min(1/|G|, 1/eps); rsq(0) = +inf
+    float inv = fminf(__builtin_amdgcn_rsqf(g2), 1.0f / P.grad_eps);
     float gh[3] = {g[0] * inv, g[1] * inv, g[2] * inv};
-    float L[3];
+    float L[3], H[3];
     if (P.light_is_point) {
         float q[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) q[a] = P.light[a] - (float)pv[a] * P.s[a];
-        float ql = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
-        float qi = ql > 0.0f ? 1.0f / ql : 0.0f;
+        float qi = rsq_or_zero(fmaf(q[2], q[2], fmaf(q[1], q[1], q[0] * q[0])));
         L[0] = q[0] * qi; L[1] = q[1] * qi; L[2] = q[2] * qi;
+        if (P.shade == RC_SHADE_BLINN_PHONG) {
+            float h[3] = {L[0] + rs.v[0], L[1] + rs.v[1], L[2] + rs.v[2]};
+            float hi = rsq_or_zero(fmaf(h[2], h[2], fmaf(h[1], h[1], h[0] * h[0])));
+            H[0] = h[0] * hi; H[1] = h[1] * hi; H[2] = h[2] * hi;
+        }
     } else {
         L[0] = P.light[0]; L[1] = P.light[1]; L[2] = P.light[2];
+        H[0] = rs.h[0]; H[1] = rs.h[1]; H[2] = rs.h[2];
     }
     if (P.shade == RC_SHADE_PAPER_LAMBERT) {
         // Listing 3: illum = dot(normalize(lightPosition - pos), norm), unclamped
-        float illum = L[0] * gh[0] + L[1] * gh[1] + L[2] * gh[2];
+        float illum = fmaf(L[2], gh[2], fmaf(L[1], gh[1], L[0] * gh[0]));
         c[0] = rgba.x * illum; c[1] = rgba.y * illum; c[2] = rgba.z * illum;
         return;
     }
-    float h[3] = {L[0] + dneg[0], L[1] + dneg[1], L[2] + dneg[2]};
-    float hl = sqrtf(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
-    float hi = hl > 0.0f ? 1.0f / hl : 0.0f;
-    float nl = -(gh[0] * L[0] + gh[1] * L[1] + gh[2] * L[2]);
-    float nh = -(gh[0] * h[0] + gh[1] * h[1] + gh[2] * h[2]) * hi;
+    float nl = -fmaf(gh[2], L[2], fmaf(gh[1], L[1], gh[0] * L[0]));
+    float nh = -fmaf(gh[2], H[2], fmaf(gh[1], H[1], gh[0] * H[0]));
     float diff = fmaxf(nl, 0.0f);
-    float spec = nh > 0.0f ? exp2f(P.shininess * log2f(nh)) : (P.shininess == 0.0f ? 1.0f : 0.0f);
-    float k = P.ka + P.kd * diff;
-    c[0] = fmaf(rgba.x, k, P.ks * spec);
-    c[1] = fmaf(rgba.y, k, P.ks * spec);
-    c[2] = fmaf(rgba.z, k, P.ks * spec);
+    float spec = nh > 0.0f ? __builtin_amdgcn_exp2f(P.shininess * __builtin_amdgcn_logf(nh))
+                           : (P.shininess == 0.0f ? 1.0f : 0.0f);
+    float k = fmaf(P.kd, diff, P.ka);
+    float ks = P.ks * spec;
+    c[0] = fmaf(rgba.x, k, ks);
+    c[1] = fmaf(rgba.y, k, ks);
+    c[2] = fmaf(rgba.z, k, ks);
 }
 
 // ---------------------------------------------------------------- LDS staging
@@ -452,7 +479,7 @@ struct Chunk {
 // gradient, shading and compositing.  Returns true when the ray terminates.
 template <typename VT, int OP, typename Src>
 __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& src, const Cell& C,
-                                             const double pv[3], const float dneg[3],
+                                             const double pv[3], const RayShade& rs,
                                              LaneState& S) {
     int ox[4], oy[4], oz[4];
     src.offsets(C, ox, oy, oz);
@@ -465,7 +492,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     if (P.shade != RC_SHADE_NONE) {
         float g[3];
         gradient<VT, OP>(P, src.base, ox, oy, oz, C, g);
-        shade(P, rgba, g, pv, dneg, c);
+        shade(P, rgba, g, pv, rs, c);
     }
     float ta = S.T * a;
     S.Cr = fmaf(ta, c[0], S.Cr);
@@ -483,7 +510,7 @@ template <typename VT, int OP>
 __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
                                             const LdsSrc<VT>& lsrc, const GlobalSrc<VT>& gsrc,
                                             bool staged, const Chunk& ch, long long kstop,
-                                            const float dneg[3], LaneState& S) {
+                                            const RayShade& rs, LaneState& S) {
     for (long long k = S.k; k <= kstop; ++k) {
         Cell C;
         double pv[3];
@@ -506,8 +533,8 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
         for (int a = 0; a < 3; ++a)
             in = in && C.c[a] - 1 >= ch.lo[a] && C.c[a] + 2 < ch.lo[a] + ch.dim[a];
         S.direct += in ? 0u : 1u;
-        bool term = in ? shade_sample<VT, OP>(P, lsrc, C, pv, dneg, S)
-                       : shade_sample<VT, OP>(P, gsrc, C, pv, dneg, S);
+        bool term = in ? shade_sample<VT, OP>(P, lsrc, C, pv, rs, S)
+                       : shade_sample<VT, OP>(P, gsrc, C, pv, rs, S);
         if (term) {
             S.k_term = k;
             S.done = true;
@@ -535,7 +562,8 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     // Staging pays off when samples need the stencil neighbourhood; an
     // unshaded march reads 8 voxels per sample and gathers them directly.
     const bool stage = P.shade != RC_SHADE_NONE;
-    const float dneg[3] = {(float)-R.d[0], (float)-R.d[1], (float)-R.d[2]};
+    RayShade rs;
+    ray_shade(P, R, rs);
     const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
     const int cap = kWaveLdsBytes / (int)sizeof(VT);
     int len = kChunkInit;
@@ -626,7 +654,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
         }
         LdsSrc<VT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1]};
         if (active && kstop >= S.k)
-            run_samples<VT, OP>(P, R, lsrc, gsrc, fits, ch, kstop, dneg, S);
+            run_samples<VT, OP>(P, R, lsrc, gsrc, fits, ch, kstop, rs, S);
         if (fits) wave_lds_sync();
         if (active && !S.done && kstop >= S.k) S.k = kstop + 1;
     }
