@@ -249,6 +249,30 @@ rc_status rc_render_batch(const rc_batch_item* items, int n, const rc_batch_conf
 rc_status rc_batch_autotune(const rc_batch_item* items, int n, const char* cache_path,
                             void* stream, rc_batch_config* out);
 
+/* ------------------------------------------------------------------------
+ * Several views of one volume.  The same volume, table, shading and options
+ * rendered from n_views cameras with one launch per 16 views, so small
+ * images share the GPU.  Equivalent to n_views rc_render /
+ * rc_render_backward calls (Section 3.10: rays are independent).
+ * ---------------------------------------------------------------------- */
+/*   cams      host array [n_views]
+ *   out_rgba  host array [n_views] of device pointers, [H_v][W_v][4] each
+ *   aux       NULL, or host array [n_views] of device pointers (entries may be NULL)
+ * Errors: as rc_render, with the failing view in rc_last_error. */
+rc_status rc_render_views(const rc_volume* vol, const rc_camera* cams, int n_views,
+                          const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                          const rc_options* opt, float* const* out_rgba, rc_aux* const* aux,
+                          void* stream);
+
+/* Reverse mode of rc_render_views (shading NONE): aux[v] and grad_rgba[v] are
+ * view v's forward aux and dL/d(rgba); all views accumulate (+=) into one
+ * grad_volume_dev and one grad_tf_dev.  Errors: as rc_render_backward. */
+rc_status rc_render_backward_views(const rc_volume* vol, const rc_camera* cams, int n_views,
+                                   const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                                   const rc_options* opt, const rc_aux* const* aux,
+                                   const float* const* grad_rgba, float* grad_volume_dev,
+                                   float* grad_tf_dev, void* stream);
+
 /* Release a handle and its device memory (synchronises with the device).
  * NULL is ignored. */
 void rc_destroy_volume(rc_volume* vol);

@@ -19,7 +19,7 @@ __all__ = [
     "rc_render", "rc_render_backward", "rc_destroy_volume", "rc_last_error", "RenderFn",
     "camera_struct", "shading_struct", "options_struct", "library_path",
     "Batch", "rc_batch_create", "rc_batch_render", "rc_batch_destroy", "rc_render_batch",
-    "rc_batch_autotune",
+    "rc_batch_autotune", "rc_render_views", "rc_render_backward_views", "RenderViewsFn",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -128,6 +128,14 @@ def _L():
         L.rc_render_batch.argtypes = [bi, C.c_int, bc, vp]
         L.rc_batch_autotune.restype = C.c_int
         L.rc_batch_autotune.argtypes = [bi, C.c_int, C.c_char_p, vp, bc]
+        pp = C.POINTER(vp)
+        L.rc_render_views.restype = C.c_int
+        L.rc_render_views.argtypes = [vp, C.POINTER(rc_camera), C.c_int, vp, C.c_int,
+                                      C.POINTER(rc_shading), C.POINTER(rc_options), pp, pp, vp]
+        L.rc_render_backward_views.restype = C.c_int
+        L.rc_render_backward_views.argtypes = [vp, C.POINTER(rc_camera), C.c_int, vp, C.c_int,
+                                               C.POINTER(rc_shading), C.POINTER(rc_options), pp,
+                                               pp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -397,3 +405,75 @@ def rc_batch_autotune(items, cache_path=None, stream=None) -> dict:
     _check(_L().rc_batch_autotune(arr, len(items), path, _stream(stream), C.byref(out)))
     return {"tile_w": out.tile_w, "waves_per_wg": out.waves_per_wg, "wg_per_cu": out.wg_per_cu,
             "order": out.order}
+
+
+# ---------------------------------------------------------------- several views of one volume
+def _ptr_array(tensors):
+    return (C.c_void_p * len(tensors))(*[t.data_ptr() if t is not None else None for t in tensors])
+
+
+def rc_render_views(vol: Volume, cameras, tf: torch.Tensor, shading: dict, options: dict,
+                    outs=None, auxes=None, stream=None):
+    """Render len(cameras) views in as few launches as possible; returns the
+    list of [H,W,4] outputs."""
+    _check_tf(tf)
+    n = len(cameras)
+    if outs is None:
+        outs = [torch.empty((int(c["height"]), int(c["width"]), 4), dtype=torch.float32,
+                            device=tf.device) for c in cameras]
+    for c, o in zip(cameras, outs):
+        if o.shape != (int(c["height"]), int(c["width"]), 4) or o.dtype != torch.float32 \
+                or not o.is_contiguous():
+            raise ValueError("each output must be a contiguous float32 [H,W,4] tensor")
+    cams = (rc_camera * n)(*[camera_struct(c) for c in cameras])
+    sh, opt = shading_struct(shading), options_struct(options)
+    aux_arr = _ptr_array(auxes) if auxes is not None else None
+    _check(_L().rc_render_views(vol.handle, cams, n, _ptr(tf), tf.shape[0], C.byref(sh),
+                                C.byref(opt), _ptr_array(outs), aux_arr, _stream(stream)))
+    return outs
+
+
+def rc_render_backward_views(vol: Volume, cameras, tf: torch.Tensor, shading: dict, options: dict,
+                             auxes, grads, grad_volume=None, grad_tf=None, stream=None):
+    """Accumulate dL/dvolume and dL/dtf over all views; returns both."""
+    _check_tf(tf)
+    n = len(cameras)
+    if grad_volume is None:
+        grad_volume = torch.zeros(vol.shape, dtype=torch.float32, device=tf.device)
+    if grad_tf is None:
+        grad_tf = torch.zeros_like(tf)
+    grads = [g.contiguous().float() for g in grads]
+    cams = (rc_camera * n)(*[camera_struct(c) for c in cameras])
+    sh, opt = shading_struct(shading), options_struct(options)
+    _check(_L().rc_render_backward_views(vol.handle, cams, n, _ptr(tf), tf.shape[0], C.byref(sh),
+                                         C.byref(opt), _ptr_array(auxes), _ptr_array(grads),
+                                         _ptr(grad_volume), _ptr(grad_tf), _stream(stream)))
+    return grad_volume, grad_tf
+
+
+class RenderViewsFn(torch.autograd.Function):
+    """Differentiable unshaded render of several views of one volume, all of
+    one image size: (volume float32, tf) -> rgba [V,H,W,4].  One launch for
+    the forward, one for the reverse pass (per 16 views)."""
+
+    @staticmethod
+    def forward(ctx, volume, tf, handle, cameras, shading, options):
+        volume = volume.contiguous()
+        tf = tf.contiguous()
+        rc_update_volume(handle, volume)
+        H, W = int(cameras[0]["height"]), int(cameras[0]["width"])
+        out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=tf.device)
+        aux = torch.empty((len(cameras), H, W), dtype=torch.int64, device=tf.device)
+        rc_render_views(handle, cameras, tf, shading, options, outs=list(out.unbind(0)),
+                        auxes=list(aux.unbind(0)))
+        ctx.save_for_backward(tf, aux)
+        ctx.handle, ctx.cameras, ctx.shading, ctx.options = handle, cameras, shading, options
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        tf, aux = ctx.saved_tensors
+        g = grad_out.float().contiguous()
+        gv, gtf = rc_render_backward_views(ctx.handle, ctx.cameras, tf, ctx.shading, ctx.options,
+                                           list(aux.unbind(0)), list(g.unbind(0)))
+        return gv, gtf, None, None, None, None

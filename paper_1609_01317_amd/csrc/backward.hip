@@ -10,8 +10,6 @@
 namespace rc {
 
 struct BackwardParams {
-    const rc_aux* aux;
-    const float4* grad;     // dL/d(rgba) per pixel
     float* dvol;            // [nz][ny][nx]
     float* dtf;             // [M][4]
     int lds_tf;             // 1: accumulate the table gradient in LDS first
@@ -102,23 +100,29 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
             }
 }
 
+// One workgroup = one 16x16 pixel tile of one view; views own consecutive
+// runs of workgroups (ViewSet::block_off).
 template <typename VT>
-__global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, BackwardParams Bp) {
+__global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
     extern __shared__ float lds[];
     if (Bp.lds_tf) {
         for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) lds[i] = 0.0f;
         __syncthreads();
     }
-    int tiles_x = (P.W + kBwdTile - 1) / kBwdTile;
-    int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    int b = blockIdx.x, v = 0;
+    while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
+    const ViewParams& V = S.v[v];
+    b -= S.block_off[v];
+    int tiles_x = (V.W + kBwdTile - 1) / kBwdTile;
+    int tx = b % tiles_x, ty = b / tiles_x;
     int px = tx * kBwdTile + (threadIdx.x % kBwdTile);
     int py = ty * kBwdTile + (threadIdx.x / kBwdTile);
-    if (px < P.W && py < P.H) {
+    if (px < V.W && py < V.H) {
         Ray R;
-        setup_ray(P, px, py, R);
-        long long pix = (long long)py * P.W + px;
-        rc_aux ax = Bp.aux[pix];
-        float4 g = Bp.grad[pix];
+        setup_ray(P, V, px, py, R);
+        long long pix = (long long)py * V.W + px;
+        rc_aux ax = V.aux[pix];
+        float4 g = V.grad[pix];
         long long last = ax.k_last;
         if (R.K >= 0 && last >= 0 && last <= R.K) {
             // Anchor: the last index a whose front transmittance T_a is at
@@ -171,35 +175,75 @@ __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, BackwardParam
 
 using namespace rc;
 
+static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n_views,
+                                const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                                const rc_options* opt, const rc_aux* const* aux,
+                                const float* const* grad_rgba, float* grad_volume_dev,
+                                float* grad_tf_dev, hipStream_t s) {
+    for (int i = 0; i < n_views; ++i) {
+        rc_status st = check_render_args(v, &cams[i], tf_rgba_dev, tf_len, sh, opt);
+        if (st != RC_OK) return n_views > 1 ? fail(st, "view %d: %s", i, rc_last_error()) : st;
+    }
+    if (sh->model != RC_SHADE_NONE)
+        return fail(RC_E_UNSUPPORTED, "rc_render_backward: only shading NONE is differentiated");
+    for (int i = 0; i < n_views; ++i)
+        if (!aux[i] || !grad_rgba[i])
+            return fail(RC_E_INVALID, "rc_render_backward: aux/grad pointers must not be NULL");
+    if (!grad_volume_dev || !grad_tf_dev)
+        return fail(RC_E_INVALID, "rc_render_backward: aux/grad pointers must not be NULL");
+    RenderParams P;
+    fill_render_params(P, v, &cams[0], tf_rgba_dev, tf_len, sh, opt);
+    BackwardParams Bp;
+    Bp.dvol = grad_volume_dev;
+    Bp.dtf = grad_tf_dev;
+    Bp.lds_tf = tf_len <= kBwdLdsEntries;
+    size_t lds = Bp.lds_tf ? (size_t)tf_len * 4 * sizeof(float) : 0;
+    for (int first = 0; first < n_views; first += kMaxViews) {
+        ViewSet S;
+        S.n = n_views - first < kMaxViews ? n_views - first : kMaxViews;
+        int off = 0;
+        for (int j = 0; j < S.n; ++j) {
+            ViewParams& V = S.v[j];
+            fill_view(V, &cams[first + j]);
+            V.aux = (rc_aux*)aux[first + j];
+            V.grad = (const float4*)grad_rgba[first + j];
+            S.block_off[j] = off;
+            off += ((V.W + kBwdTile - 1) / kBwdTile) * ((V.H + kBwdTile - 1) / kBwdTile);
+        }
+        S.block_off[S.n] = off;
+        dim3 grid((unsigned)off), block(kBwdTile * kBwdTile);
+        if (v->dtype == RC_U8)
+            hipLaunchKernelGGL(raycast_bwd<uint8_t>, grid, block, lds, s, P, S, Bp);
+        else if (v->dtype == RC_U16)
+            hipLaunchKernelGGL(raycast_bwd<uint16_t>, grid, block, lds, s, P, S, Bp);
+        else
+            hipLaunchKernelGGL(raycast_bwd<float>, grid, block, lds, s, P, S, Bp);
+        RC_HIP(hipGetLastError());
+    }
+    return RC_OK;
+}
+
 extern "C" rc_status rc_render_backward(const rc_volume* v, const rc_camera* cam,
                                         const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
                                         const rc_options* opt, const rc_aux* aux_dev,
                                         const float* grad_rgba_dev, float* grad_volume_dev,
                                         float* grad_tf_dev, void* stream) {
-    rc_status st = check_render_args(v, cam, tf_rgba_dev, tf_len, sh, opt);
-    if (st != RC_OK) return st;
-    if (sh->model != RC_SHADE_NONE)
-        return fail(RC_E_UNSUPPORTED, "rc_render_backward: only shading NONE is differentiated");
-    if (!aux_dev || !grad_rgba_dev || !grad_volume_dev || !grad_tf_dev)
-        return fail(RC_E_INVALID, "rc_render_backward: aux/grad pointers must not be NULL");
-    RenderParams P;
-    fill_render_params(P, v, cam, tf_rgba_dev, tf_len, sh, opt);
-    BackwardParams Bp;
-    Bp.aux = aux_dev;
-    Bp.grad = (const float4*)grad_rgba_dev;
-    Bp.dvol = grad_volume_dev;
-    Bp.dtf = grad_tf_dev;
-    Bp.lds_tf = tf_len <= kBwdLdsEntries;
-    size_t lds = Bp.lds_tf ? (size_t)tf_len * 4 * sizeof(float) : 0;
-    int tiles = ((cam->width + kBwdTile - 1) / kBwdTile) * ((cam->height + kBwdTile - 1) / kBwdTile);
-    hipStream_t s = (hipStream_t)stream;
-    dim3 grid((unsigned)tiles), block(kBwdTile * kBwdTile);
-    if (v->dtype == RC_U8)
-        hipLaunchKernelGGL(raycast_bwd<uint8_t>, grid, block, lds, s, P, Bp);
-    else if (v->dtype == RC_U16)
-        hipLaunchKernelGGL(raycast_bwd<uint16_t>, grid, block, lds, s, P, Bp);
-    else
-        hipLaunchKernelGGL(raycast_bwd<float>, grid, block, lds, s, P, Bp);
-    RC_HIP(hipGetLastError());
-    return RC_OK;
+    if (!cam) return check_render_args(v, cam, tf_rgba_dev, tf_len, sh, opt);
+    const rc_aux* aux[1] = {aux_dev};
+    const float* grad[1] = {grad_rgba_dev};
+    return backward_views(v, cam, 1, tf_rgba_dev, tf_len, sh, opt, aux, grad, grad_volume_dev,
+                          grad_tf_dev, (hipStream_t)stream);
+}
+
+extern "C" rc_status rc_render_backward_views(const rc_volume* v, const rc_camera* cams,
+                                              int n_views, const float* tf_rgba_dev, int tf_len,
+                                              const rc_shading* sh, const rc_options* opt,
+                                              const rc_aux* const* aux,
+                                              const float* const* grad_rgba,
+                                              float* grad_volume_dev, float* grad_tf_dev,
+                                              void* stream) {
+    if (!cams || !aux || !grad_rgba || n_views < 1)
+        return fail(RC_E_INVALID, "rc_render_backward_views: need n_views >= 1 and non-NULL arrays");
+    return backward_views(v, cams, n_views, tf_rgba_dev, tf_len, sh, opt, aux, grad_rgba,
+                          grad_volume_dev, grad_tf_dev, (hipStream_t)stream);
 }

@@ -105,15 +105,15 @@ __global__ __launch_bounds__(256) void raycast_batch(const RenderParams* __restr
         int tile = w - tile_off[lo];
         const RenderParams& P = items[item];
         switch (kinds[item]) {
-            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL>(P, tile, lane, (uint8_t*)lds); break;
-            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D>(P, tile, lane, (uint8_t*)lds); break;
-            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane, (uint8_t*)lds); break;
-            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL>(P, tile, lane, (uint16_t*)lds); break;
-            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D>(P, tile, lane, (uint16_t*)lds); break;
-            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane, (uint16_t*)lds); break;
-            case 6: render_tile<float, RC_GRAD_CENTRAL>(P, tile, lane, (float*)lds); break;
-            case 7: render_tile<float, RC_GRAD_SOBEL3D>(P, tile, lane, (float*)lds); break;
-            default: render_tile<float, RC_GRAD_ZUCKER_HUMMEL>(P, tile, lane, (float*)lds); break;
+            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL>(P, P.view, tile, lane, (uint8_t*)lds); break;
+            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D>(P, P.view, tile, lane, (uint8_t*)lds); break;
+            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL>(P, P.view, tile, lane, (uint8_t*)lds); break;
+            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL>(P, P.view, tile, lane, (uint16_t*)lds); break;
+            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D>(P, P.view, tile, lane, (uint16_t*)lds); break;
+            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL>(P, P.view, tile, lane, (uint16_t*)lds); break;
+            case 6: render_tile<float, RC_GRAD_CENTRAL>(P, P.view, tile, lane, (float*)lds); break;
+            case 7: render_tile<float, RC_GRAD_SOBEL3D>(P, P.view, tile, lane, (float*)lds); break;
+            default: render_tile<float, RC_GRAD_ZUCKER_HUMMEL>(P, P.view, tile, lane, (float*)lds); break;
         }
     }
 }
@@ -178,11 +178,11 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
         if (!it.out_rgba_dev) return fail(RC_E_INVALID, "item %d: out_rgba_dev is NULL", i);
         if (it.reserved != 0) return fail(RC_E_INVALID, "item %d: reserved field must be 0", i);
         fill_render_params(P[i], it.vol, &it.cam, it.tf_rgba_dev, it.tf_len, &it.sh, &it.opt);
-        set_tiling(P[i], c.tile_w);
-        P[i].out = (float4*)it.out_rgba_dev;
-        P[i].aux = it.aux_dev;
+        set_tiling(P[i].view, c.tile_w);
+        P[i].view.out = (float4*)it.out_rgba_dev;
+        P[i].view.aux = it.aux_dev;
         kinds[i] = (int)it.vol->dtype * 3 + it.opt.gradient_op;
-        tiles[i] = P[i].n_tiles;
+        tiles[i] = P[i].view.n_tiles;
         if (it.opt.skip_empty) {
             MaskJob J;
             J.range = it.vol->brick_range;

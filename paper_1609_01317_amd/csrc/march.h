@@ -75,22 +75,23 @@ struct Ray {
     long long K;        // index of the last lattice sample, -1 on a miss
 };
 
-__device__ inline void setup_ray(const RenderParams& P, int px, int py, Ray& R) {
-    double x = 2.0 * ((double)px + 0.5) / (double)P.W - 1.0;
-    double y = 1.0 - 2.0 * ((double)py + 0.5) / (double)P.H;
-    if (P.projection == RC_PERSPECTIVE) {
-        double th = P.tan_half;
-        double t0 = P.f[0] + x * th * P.aspect * P.r[0] + y * th * P.u[0];
-        double t1 = P.f[1] + x * th * P.aspect * P.r[1] + y * th * P.u[1];
-        double t2 = P.f[2] + x * th * P.aspect * P.r[2] + y * th * P.u[2];
+__device__ inline void setup_ray(const RenderParams& P, const ViewParams& V, int px, int py,
+                                 Ray& R) {
+    double x = 2.0 * ((double)px + 0.5) / (double)V.W - 1.0;
+    double y = 1.0 - 2.0 * ((double)py + 0.5) / (double)V.H;
+    if (V.projection == RC_PERSPECTIVE) {
+        double th = V.tan_half;
+        double t0 = V.f[0] + x * th * V.aspect * V.r[0] + y * th * V.u[0];
+        double t1 = V.f[1] + x * th * V.aspect * V.r[1] + y * th * V.u[1];
+        double t2 = V.f[2] + x * th * V.aspect * V.r[2] + y * th * V.u[2];
         double n = sqrt(t0 * t0 + t1 * t1 + t2 * t2);
         double s = n > 0.0 ? 1.0 / n : 0.0;
         R.d[0] = t0 * s; R.d[1] = t1 * s; R.d[2] = t2 * s;
-        R.o[0] = P.eye[0]; R.o[1] = P.eye[1]; R.o[2] = P.eye[2];
+        R.o[0] = V.eye[0]; R.o[1] = V.eye[1]; R.o[2] = V.eye[2];
     } else {
         for (int a = 0; a < 3; ++a) {
-            R.d[a] = P.f[a];
-            R.o[a] = P.eye[a] + (x * P.aspect * P.r[a] + y * P.u[a]) * P.ortho_half;
+            R.d[a] = V.f[a];
+            R.o[a] = V.eye[a] + (x * V.aspect * V.r[a] + y * V.u[a]) * V.ortho_half;
         }
     }
     // slab method, t >= 0
@@ -674,22 +675,23 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
 // tile's row-major index in the image.  Lanes outside the image take part
 // in the wave-wide steps without a ray.
 template <typename VT, int OP>
-__device__ inline void render_tile(const RenderParams& P, int tile, int lane, VT* lds) {
-    const int tw = P.tile_w, th = 64 / P.tile_w;
-    int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+__device__ inline void render_tile(const RenderParams& P, const ViewParams& V, int tile, int lane,
+                                   VT* lds) {
+    const int tw = V.tile_w, th = 64 / V.tile_w;
+    int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
     int px = tx * tw + (lane % tw), py = ty * th + (lane / tw);
-    bool valid = px < P.W && py < P.H;
+    bool valid = px < V.W && py < V.H;
     Ray R;
     R.K = -1;
     R.t_in = 0.0;
     for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = 0.0;
-    if (valid) setup_ray(P, px, py, R);
+    if (valid) setup_ray(P, V, px, py, R);
     MarchOut M;
     march_wave<VT, OP>(P, R, valid, lds, lane, M);
     if (valid) {
-        long long pix = (long long)py * P.W + px;
-        P.out[pix] = M.rgba;
-        if (P.aux) P.aux[pix] = rc_aux{M.k_last, M.T};
+        long long pix = (long long)py * V.W + px;
+        V.out[pix] = M.rgba;
+        if (V.aux) V.aux[pix] = rc_aux{M.k_last, M.T};
     }
     if (P.stats) {
         unsigned lat = wave_sum(R.K >= 0 ? (unsigned)(M.k_last + 1) : 0u);

@@ -54,13 +54,21 @@ __host__ __device__ inline int off_y(int y, int sy) { return (y >> 3) * sy + ((i
 __host__ __device__ inline int off_z(int z, int sz) { return (z >> 3) * sz + ((int)spread3(z & 7) << 2); }
 
 // ---------------------------------------------------------------- render parameters
-struct RenderParams {
-    // camera frame and image (FP64: ray set-up is exact to double)
+// One image: camera frame (FP64: ray set-up is exact to double), tiling
+// and the per-image buffers.
+struct ViewParams {
     double eye[3], f[3], r[3], u[3];
     double tan_half, aspect, ortho_half;
     int projection, W, H;
     int tile_w;                 // tile width in pixels (tile height = 64 / tile_w)
     int tiles_x, n_tiles;
+    float4* out;
+    rc_aux* aux;
+    const float4* grad;         // reverse pass: dL/d(rgba)
+};
+
+struct RenderParams {
+    ViewParams view;            // the image of a single render / batch item
     // sampling box (world) and lattice
     double lo[3], hi[3];
     double step;
@@ -88,11 +96,18 @@ struct RenderParams {
     float tau;
     int skip;
     const uint8_t* empty;       // per-brick flag, 1 = every sample has alpha 0
-    // outputs
-    float4* out;
-    rc_aux* aux;
     rc_stats* stats;            // kStatSlots consecutive copies, or null
 };
+
+// Several images of one volume in one launch (kernel-argument block).
+constexpr int kMaxViews = 16;
+struct ViewSet {
+    int n;
+    int block_off[kMaxViews + 1];   // first block of each view
+    ViewParams v[kMaxViews];
+};
+static_assert(sizeof(RenderParams) + sizeof(ViewSet) <= 3800,
+              "kernel arguments of the multi-view kernels must stay below 4 KiB");
 
 // Host-side preparation shared by the forward, reverse and batch paths.
 rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const float* tf, int tf_len,
@@ -103,7 +118,8 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
 // `prefix` (tf_len + 1 ints) as scratch.
 rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
                             int* prefix, hipStream_t st);
-void set_tiling(RenderParams& P, int tile_w);   // tile_w in {4, 8, 16, 32, 64}
+void set_tiling(ViewParams& V, int tile_w);     // tile_w in {4, 8, 16, 32, 64}
+void fill_view(ViewParams& V, const rc_camera* cam);
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
 
 }  // namespace rc

@@ -92,8 +92,21 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
 template <typename VT, int OP>
 __global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
     __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
-    int tile = tile_of_block(blockIdx.x, P.tiles_x, P.n_tiles / P.tiles_x);
-    if (tile >= 0) render_tile<VT, OP>(P, tile, threadIdx.x, (VT*)lds);
+    const ViewParams& V = P.view;
+    int tile = tile_of_block(blockIdx.x, V.tiles_x, V.n_tiles / V.tiles_x);
+    if (tile >= 0) render_tile<VT, OP>(P, V, tile, threadIdx.x, (VT*)lds);
+}
+
+// Several views of one volume: each view owns a run of blocks (a multiple of
+// the XCD group size, so the group dealing above holds inside every view).
+template <typename VT, int OP>
+__global__ __launch_bounds__(64) void raycast_views(RenderParams P, ViewSet S) {
+    __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
+    int b = blockIdx.x, v = 0;
+    while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
+    const ViewParams& V = S.v[v];
+    int tile = tile_of_block(b - S.block_off[v], V.tiles_x, V.n_tiles / V.tiles_x);
+    if (tile >= 0) render_tile<VT, OP>(P, V, tile, threadIdx.x, (VT*)lds);
 }
 
 // ---------------------------------------------------------------- counters
@@ -116,7 +129,8 @@ __global__ void stats_fold(const unsigned long long* __restrict__ slots,
 
 template <typename VT>
 static void launch_fwd_t(const RenderParams& P, int op, hipStream_t st) {
-    dim3 grid((unsigned)group_grid_blocks(P.tiles_x, P.n_tiles / P.tiles_x)), block(64);
+    const ViewParams& V = P.view;
+    dim3 grid((unsigned)group_grid_blocks(V.tiles_x, V.n_tiles / V.tiles_x)), block(64);
     if (op == RC_GRAD_CENTRAL)
         hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_CENTRAL>), grid, block, 0, st, P);
     else if (op == RC_GRAD_SOBEL3D)
@@ -129,6 +143,26 @@ rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t
     if (dt == RC_U8) launch_fwd_t<uint8_t>(P, op, st);
     else if (dt == RC_U16) launch_fwd_t<uint16_t>(P, op, st);
     else launch_fwd_t<float>(P, op, st);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
+template <typename VT>
+static void launch_views_t(const RenderParams& P, const ViewSet& S, int op, hipStream_t st) {
+    dim3 grid((unsigned)S.block_off[S.n]), block(64);
+    if (op == RC_GRAD_CENTRAL)
+        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_CENTRAL>), grid, block, 0, st, P, S);
+    else if (op == RC_GRAD_SOBEL3D)
+        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_SOBEL3D>), grid, block, 0, st, P, S);
+    else
+        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_ZUCKER_HUMMEL>), grid, block, 0, st, P, S);
+}
+
+static rc_status launch_views(const RenderParams& P, const ViewSet& S, rc_dtype dt, int op,
+                              hipStream_t st) {
+    if (dt == RC_U8) launch_views_t<uint8_t>(P, S, op, st);
+    else if (dt == RC_U16) launch_views_t<uint16_t>(P, S, op, st);
+    else launch_views_t<float>(P, S, op, st);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }
@@ -235,11 +269,31 @@ rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const floa
     return RC_OK;
 }
 
-void set_tiling(RenderParams& P, int tile_w) {
+void set_tiling(ViewParams& V, int tile_w) {
     int th = 64 / tile_w;
-    P.tile_w = tile_w;
-    P.tiles_x = (P.W + tile_w - 1) / tile_w;
-    P.n_tiles = P.tiles_x * ((P.H + th - 1) / th);
+    V.tile_w = tile_w;
+    V.tiles_x = (V.W + tile_w - 1) / tile_w;
+    V.n_tiles = V.tiles_x * ((V.H + th - 1) / th);
+}
+
+void fill_view(ViewParams& V, const rc_camera* cam) {
+    double tmp[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1],
+                     cam->target[2] - cam->eye[2]};
+    normalize3(tmp, V.f);
+    cross3(V.f, cam->up, tmp);
+    normalize3(tmp, V.r);
+    cross3(V.r, V.f, V.u);
+    for (int a = 0; a < 3; ++a) V.eye[a] = cam->eye[a];
+    V.tan_half = std::tan(cam->fov_y_deg * 0.5 * M_PI / 180.0);
+    V.aspect = (double)cam->width / (double)cam->height;
+    V.ortho_half = cam->ortho_height * 0.5;
+    V.projection = cam->projection;
+    V.W = cam->width;
+    V.H = cam->height;
+    set_tiling(V, 8);
+    V.out = nullptr;
+    V.aux = nullptr;
+    V.grad = nullptr;
 }
 
 static double op_gain(int op) {
@@ -258,20 +312,7 @@ static double op_gain(int op) {
 
 void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* cam,
                         const float* tf, int tf_len, const rc_shading* sh, const rc_options* opt) {
-    double tmp[3] = {cam->target[0] - cam->eye[0], cam->target[1] - cam->eye[1],
-                     cam->target[2] - cam->eye[2]};
-    normalize3(tmp, P.f);
-    cross3(P.f, cam->up, tmp);
-    normalize3(tmp, P.r);
-    cross3(P.r, P.f, P.u);
-    for (int a = 0; a < 3; ++a) P.eye[a] = cam->eye[a];
-    P.tan_half = std::tan(cam->fov_y_deg * 0.5 * M_PI / 180.0);
-    P.aspect = (double)cam->width / (double)cam->height;
-    P.ortho_half = cam->ortho_height * 0.5;
-    P.projection = cam->projection;
-    P.W = cam->width;
-    P.H = cam->height;
-    set_tiling(P, 8);
+    fill_view(P.view, cam);
     sampling_box(v, opt, P.lo, P.hi);
     P.step = opt->step;
     for (int a = 0; a < 3; ++a) {
@@ -305,8 +346,6 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     P.tau = opt->ert_threshold;
     P.skip = opt->skip_empty;
     P.empty = nullptr;
-    P.out = nullptr;
-    P.aux = nullptr;
     P.stats = nullptr;
 }
 
@@ -324,8 +363,8 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
     hipStream_t s = (hipStream_t)stream;
     RenderParams P;
     fill_render_params(P, v, cam, tf_rgba_dev, tf_len, sh, opt);
-    P.out = (float4*)out_rgba_dev;
-    P.aux = aux_dev;
+    P.view.out = (float4*)out_rgba_dev;
+    P.view.aux = aux_dev;
     // per-render scratch: counter slots, empty mask, table prefix counts
     const size_t stat_bytes = stats_dev ? sizeof(rc_stats) * kStatSlots : 0;
     const size_t mask_bytes = opt->skip_empty ? (((size_t)v->nbricks + 255) & ~(size_t)255) : 0;
@@ -352,6 +391,53 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
                            (unsigned long long*)stats_dev);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) st = hip_fail(e, "stats_fold");
+    }
+    if (scratch) {
+        hipError_t e = hipFreeAsync(scratch, s);
+        if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    }
+    return st;
+}
+
+// Several views of one volume, table, shading and options in as few launches
+// as possible (up to kMaxViews views per launch).
+extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, int n_views,
+                                     const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                                     const rc_options* opt, float* const* out_rgba,
+                                     rc_aux* const* aux, void* stream) {
+    if (!cams || !out_rgba) return fail(RC_E_INVALID, "rc_render_views: cams/out_rgba is NULL");
+    if (n_views < 1) return fail(RC_E_INVALID, "rc_render_views: n_views must be >= 1");
+    for (int i = 0; i < n_views; ++i) {
+        rc_status st = check_render_args(v, &cams[i], tf_rgba_dev, tf_len, sh, opt);
+        if (st != RC_OK) return fail(st, "view %d: %s", i, rc_last_error());
+        if (!out_rgba[i]) return fail(RC_E_INVALID, "view %d: out_rgba is NULL", i);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    RenderParams P;
+    fill_render_params(P, v, &cams[0], tf_rgba_dev, tf_len, sh, opt);
+    rc_status st = RC_OK;
+    void* scratch = nullptr;
+    if (opt->skip_empty) {
+        const size_t mask_bytes = ((size_t)v->nbricks + 255) & ~(size_t)255;
+        RC_HIP(hipMallocAsync(&scratch, mask_bytes + sizeof(int) * ((size_t)tf_len + 1), s));
+        P.empty = (uint8_t*)scratch;
+        st = launch_empty_mask(v, tf_rgba_dev, tf_len, (uint8_t*)scratch,
+                               (int*)((char*)scratch + mask_bytes), s);
+    }
+    for (int first = 0; st == RC_OK && first < n_views; first += kMaxViews) {
+        ViewSet S;
+        S.n = n_views - first < kMaxViews ? n_views - first : kMaxViews;
+        int off = 0;
+        for (int j = 0; j < S.n; ++j) {
+            ViewParams& V = S.v[j];
+            fill_view(V, &cams[first + j]);
+            V.out = (float4*)out_rgba[first + j];
+            V.aux = aux ? aux[first + j] : nullptr;
+            S.block_off[j] = off;
+            off += group_grid_blocks(V.tiles_x, V.n_tiles / V.tiles_x);
+        }
+        S.block_off[S.n] = off;
+        st = launch_views(P, S, v->dtype, opt->gradient_op, s);
     }
     if (scratch) {
         hipError_t e = hipFreeAsync(scratch, s);

@@ -143,3 +143,72 @@ def test_c5_crop_matches_finite_differences(c5):
             (idx, fd, gv[k, j, i])
     print(f"c5 FD: {checked} voxels checked", flush=True)
     assert checked >= 20
+
+
+# ---------------------------------------------------------------- several views, one launch
+def _views_scene(n_views, seed=61, image=(40, 36)):
+    sc = W.config_small(seed=seed, dims=(21, 19, 17), dtype=np.float32, image=image,
+                        shading="none")
+    cams = [W.orbit_camera((21, 19, 17), sc.spacing, 17.0 * i, 25.0 - 3 * i, image[0], image[1])
+            for i in range(n_views)]
+    return sc, cams
+
+
+def test_render_views_equals_single_renders():
+    """20 views (two launches of at most 16), mixed image sizes, skipping on."""
+    sc = W.config_small(seed=62, dims=(30, 26, 22), dtype=np.uint16, image=(37, 29),
+                        op="sobel3d", ert=0.95, skip=True)
+    cams = [W.orbit_camera((30, 26, 22), sc.spacing, 18.0 * i, 30.0 - 4 * i, 24 + 8 * (i % 3),
+                           16 + 8 * (i % 4)) for i in range(20)]
+    vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+    rc.rc_build_bricks(vol, 8)
+    tf = to_dev(sc.tf)
+    auxes = [rc.new_aux(c) for c in cams]
+    outs = rc.rc_render_views(vol, cams, tf, sc.shading, sc.options, auxes=auxes)
+    for c, o, a in zip(cams, outs, auxes):
+        a1 = rc.new_aux(c)
+        ref = rc.rc_render(vol, c, tf, sc.shading, sc.options, aux=a1)
+        torch.cuda.synchronize()
+        assert torch.equal(o, ref) and torch.equal(a, a1)
+
+
+def test_backward_views_equals_sum_of_single_views():
+    sc, cams = _views_scene(18)
+    vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+    tf = to_dev(sc.tf)
+    auxes = [rc.new_aux(c) for c in cams]
+    rc.rc_render_views(vol, cams, tf, sc.shading, sc.options, auxes=auxes)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    grads = [torch.randn((c["height"], c["width"], 4), device="cuda", generator=gen) for c in cams]
+    gv, gt = rc.rc_render_backward_views(vol, cams, tf, sc.shading, sc.options, auxes, grads)
+    gv1 = torch.zeros_like(gv)
+    gt1 = torch.zeros_like(gt)
+    for c, a, g in zip(cams, auxes, grads):
+        rc.rc_render_backward(vol, c, tf, sc.shading, sc.options, a, g, gv1, gt1)
+    torch.cuda.synchronize()
+    assert _rel(gv.cpu().numpy(), gv1.cpu().numpy()) <= 1e-5
+    assert _rel(gt.cpu().numpy(), gt1.cpu().numpy()) <= 1e-5
+
+
+def test_render_views_fn_matches_oracle():
+    """Two views through the multi-view autograd function vs the FP64 adjoint."""
+    sc, cams = _views_scene(2, seed=63)
+    v = to_dev(sc.volume)
+    h = rc.rc_create_volume(v, sc.spacing, sc.vmin, sc.vmax)
+    vp = v.clone().requires_grad_(True)
+    tp = to_dev(sc.tf).requires_grad_(True)
+    out = rc.RenderViewsFn.apply(vp, tp, h, cams, sc.shading, sc.options)
+    rng = np.random.default_rng(63)
+    g = rng.normal(size=tuple(out.shape))
+    (out * torch.from_numpy(g).float().cuda()).sum().backward()
+    ov = oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
+    dv = np.zeros(sc.volume.shape)
+    dt = np.zeros(sc.tf.shape)
+    for i, c in enumerate(cams):
+        r = oracle.render(ov, c, sc.tf, sc.shading, sc.options)
+        err = np.abs(out[i].detach().cpu().numpy() - r["rgba"]).max()
+        assert err <= 2e-4, err
+        a, b = oracle.render_grad(ov, c, sc.tf, sc.options, g[i])
+        dv += a
+        dt += b
+    assert _rel(vp.grad.cpu().numpy(), dv) <= REL and _rel(tp.grad.cpu().numpy(), dt) <= REL
