@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 OP = {"central": 0, "sobel3d": 1, "zucker_hummel": 2}
 SHADE = {"none": 0, "blinn_phong": 1, "paper_lambert": 2}
-FLAG_HIT, FLAG_TIE, FLAG_ERT_NEAR = 1, 2, 4
+FLAG_HIT, FLAG_TIE, FLAG_ERT_NEAR, FLAG_ISO_NEAR = 1, 2, 4, 8
 
 
 def build(force: bool = True) -> str:
@@ -56,6 +56,12 @@ class _Options(C.Structure):
                 ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3)]
 
 
+class _SurfaceOptions(C.Structure):
+    _fields_ = [("step", C.c_double), ("gradient_op", C.c_int), ("iso_lo", C.c_double),
+                ("iso_hi", C.c_double), ("refine", C.c_int), ("clip_lo", C.c_double * 3),
+                ("clip_hi", C.c_double * 3)]
+
+
 _lib = None
 
 
@@ -85,6 +91,10 @@ def lib():
         L.orc_render_grad.restype = C.c_int
         L.orc_render_grad.argtypes = [C.POINTER(_Volume), C.POINTER(_Camera), dp, C.c_int,
                                       C.POINTER(_Options), lp, C.c_long, dp, dp, dp]
+        L.orc_render_surface.restype = C.c_int
+        L.orc_render_surface.argtypes = [C.POINTER(_Volume), C.POINTER(_Camera), dp, C.c_int,
+                                         C.POINTER(_Shading), C.POINTER(_SurfaceOptions), lp,
+                                         C.c_long, dp, dp, ip, ip, C.c_int]
         _lib = L
     return _lib
 
@@ -210,3 +220,38 @@ def render_grad(vol: Volume, cam, tf, options, g_rgba, pixels=None):
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return dvol, dtf
+
+
+def _surface_options(opt):
+    return _SurfaceOptions(opt["step"], OP[opt["gradient_op"]], float(opt["iso_lo"]),
+                           float(opt["iso_hi"]), int(opt["refine"]),
+                           (C.c_double * 3)(*opt["clip_lo"]), (C.c_double * 3)(*opt["clip_hi"]))
+
+
+def render_surface(vol: Volume, cam, tf, shading, options, pixels=None, threads=0):
+    """First-hit surface render of all pixels or the listed linear indices.
+
+    Returns rgba [n,4], t_hit [n] (+inf without a surface), k_hit [n] (-1)
+    and flags [n]; full frames come back as [H,W,...].
+    """
+    L = lib()
+    c, s, o = _camera(cam), _shading(shading), _surface_options(options)
+    t = np.ascontiguousarray(tf, dtype=np.float64)
+    W, H = cam["width"], cam["height"]
+    if pixels is None:
+        n, pix_p, full = W * H, None, True
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        n, pix_p, full = pix.size, pix.ctypes.data_as(C.POINTER(C.c_long)), False
+    rgba, th = np.zeros((n, 4)), np.zeros(n)
+    kh, flags = np.zeros(n, dtype=np.int32), np.zeros(n, dtype=np.int32)
+    rc = L.orc_render_surface(C.byref(vol.s), C.byref(c), _dp(t), t.shape[0], C.byref(s),
+                              C.byref(o), pix_p, n, _dp(rgba), _dp(th),
+                              kh.ctypes.data_as(C.POINTER(C.c_int)),
+                              flags.ctypes.data_as(C.POINTER(C.c_int)), int(threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    out = {"rgba": rgba, "t_hit": th, "k_hit": kh, "flags": flags}
+    if full:
+        out = {k: v.reshape((H, W) + v.shape[1:]) for k, v in out.items()}
+    return out

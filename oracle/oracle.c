@@ -496,3 +496,122 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* First-hit surface mode.  The raycaster of Section 3 draws only the   */
+/* surfaces of the objects in the volume and does not look into the     */
+/* material; Section 3.11 selects the drawn voxels by two thresholds on  */
+/* the data value (a window), and Section 3.9 states that it composites  */
+/* nothing, so a surface pixel is opaque.  Sections 3.11 and 5.1: a      */
+/* coarse forward march finds the first sample inside the window, then   */
+/* hitpoint refinement halves the step again and again, moving back from */
+/* a sample inside the window and forward from one outside it.           */
+/* Reading: "closer to the target value" is taken as "on the window side */
+/* of the boundary"; the refinement is then a bisection of the last      */
+/* coarse interval, 2^n times finer after n steps (the "64 times" that   */
+/* Section 5.1 quotes for 6 steps).  A ray whose first sample is already */
+/* inside (a clip plane through the object) is not refined.  The refined */
+/* point is shaded with the gradient there and coloured by the TF's rgb  */
+/* at its value.                                                         */
+/* ------------------------------------------------------------------ */
+static int in_window(double val, const orc_surface_options* o) {
+    return val >= o->iso_lo && val <= o->iso_hi;
+}
+
+static int near_bound(double val, const orc_surface_options* o, double eps) {
+    return fabs(val - o->iso_lo) <= eps || fabs(val - o->iso_hi) <= eps;
+}
+
+static double value_at(const orc_volume* v, const ray_setup* rs, double t, double pv[3],
+                       double pw[3]) {
+    for (int a = 0; a < 3; ++a) {
+        pw[a] = rs->o[a] + t * rs->d[a];
+        pv[a] = pw[a] / v->spacing[a];
+    }
+    return orc_sample(v, pv);
+}
+
+int orc_render_surface(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
+                       const orc_shading* sh, const orc_surface_options* opt, const long* pix,
+                       long n, double* rgba, double* t_hit, int* k_hit, int* flags, int threads) {
+    if (!opt || !sh || !rgba) return -1;
+    if (!(opt->iso_lo <= opt->iso_hi) || opt->refine < 0 || opt->refine > 60) return -1;
+    orc_options base;
+    memset(&base, 0, sizeof base);
+    base.step = opt->step;
+    base.gradient_op = opt->gradient_op;
+    for (int a = 0; a < 3; ++a) {
+        base.clip_lo[a] = opt->clip_lo[a];
+        base.clip_hi[a] = opt->clip_hi[a];
+    }
+    if (check_args(v, cam, tf, M, &base)) return -1;
+    const double eps = ORC_ISO_EPS * (v->vmax - v->vmin);
+    long total = (long)cam->width * cam->height;
+    if (!pix) n = total;
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long q = 0; q < n; ++q) {
+        long id = pix ? pix[q] : q;
+        int px = (int)(id % cam->width), py = (int)(id / cam->width);
+        ray_setup rs;
+        setup_ray(v, cam, &base, px, py, &rs);
+        double out[4] = {0, 0, 0, 0};
+        double th = INFINITY;
+        int kh = -1, fl = rs.K >= 0 ? ORC_FLAG_HIT : 0, near = 0;
+        long kmax = rs.tie && rs.K_alt > rs.K ? rs.K_alt : rs.K;
+        double pv[3], pw[3];
+        /* coarse march: first lattice sample inside the window */
+        long first = -1;
+        for (long k = 0; k <= kmax; ++k) {
+            double val = value_at(v, &rs, rs.t_in + (double)k * opt->step, pv, pw);
+            if (near_bound(val, opt, eps)) near = 1;
+            if (in_window(val, opt)) {
+                first = k;
+                break;
+            }
+        }
+        if (rs.tie && first >= 0 && first == kmax) fl |= ORC_FLAG_LATTICE_TIE;
+        if (first >= 0 && first <= rs.K) {
+            kh = (int)first;
+            double t = rs.t_in + (double)first * opt->step;
+            if (first > 0) {
+                /* hitpoint refinement: halve the step, back when inside */
+                double h = opt->step;
+                int inside = 1;
+                for (int i = 0; i < opt->refine; ++i) {
+                    h *= 0.5;
+                    t = inside ? t - h : t + h;
+                    if (i + 1 < opt->refine) {
+                        double val = value_at(v, &rs, t, pv, pw);
+                        if (near_bound(val, opt, eps)) near = 1;
+                        inside = in_window(val, opt);
+                    }
+                }
+            }
+            th = t;
+            double val = value_at(v, &rs, t, pv, pw);
+            int interior;
+            double u = value_to_u(v, val, M, &interior);
+            double col[4], c[3];
+            orc_tf(tf, M, u, col);
+            if (sh->model == ORC_SHADE_NONE) {
+                c[0] = col[0]; c[1] = col[1]; c[2] = col[2];
+            } else {
+                double g[3];
+                orc_gradient(v, opt->gradient_op, pv, g, NULL);
+                orc_shade(sh, col, g, pw, rs.d, c);
+            }
+            out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = 1.0;
+        }
+        if (near) fl |= ORC_FLAG_ISO_NEAR;
+        memcpy(rgba + q * 4, out, sizeof out);
+        if (t_hit) t_hit[q] = th;
+        if (k_hit) k_hit[q] = kh;
+        if (flags) flags[q] = fl;
+    }
+    return 0;
+}

@@ -17,6 +17,8 @@
  *   Section 3.8  Listing 3    point-light Lambert shading ("Shade")
  *   Section 3.9  eq. (6)      the transparency (compositing) formula
  *   Section 3.10              the four-step pipeline
+ *   Sections 3, 3.11, 5.1     first-hit surface mode: a value window, a
+ *                             coarse march, hitpoint refinement
  * Readings where the paper is silent (coordinate frame, camera model,
  * lattice anchoring, TF interpolation, gradient scale, Blinn-Phong
  * constants, the Zucker-Hummel mask) are listed with the functions.
@@ -40,10 +42,13 @@ enum {
     ORC_FLAG_HIT = 1,        /* the ray met the sampling box */
     ORC_FLAG_LATTICE_TIE = 2,/* (t_out-t_in)/step within ORC_TIE_EPS of an integer:
                                 rgba_alt holds the result with the other sample count */
-    ORC_FLAG_ERT_NEAR = 4    /* 1-T came within ORC_ERT_EPS of the ERT threshold */
+    ORC_FLAG_ERT_NEAR = 4,   /* 1-T came within ORC_ERT_EPS of the ERT threshold */
+    ORC_FLAG_ISO_NEAR = 8    /* surface mode: a window test that decided the result had a
+                                value within ORC_ISO_EPS*(vmax-vmin) of a window bound */
 };
 #define ORC_TIE_EPS 1e-6
 #define ORC_ERT_EPS 1e-4
+#define ORC_ISO_EPS 1e-6
 
 typedef struct {
     const double* data;      /* [nz][ny][nx] voxel values, x fastest */
@@ -116,6 +121,30 @@ int orc_render(const orc_volume* v, const orc_camera* cam, const double* tf, int
 int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
                     const orc_options* opt, const long* pix, long n, const double* g_rgba,
                     double* dvol, double* dtf);
+
+/* First-hit surface mode (Sections 3, 3.11 and 5.1). */
+typedef struct {
+    double step;             /* coarse sample distance in world units */
+    int gradient_op;         /* ORC_OP_* */
+    double iso_lo, iso_hi;   /* raw-value window drawn as the surface */
+    int refine;              /* hitpoint-refinement steps (Section 5.1: 5 to 6) */
+    double clip_lo[3], clip_hi[3];
+} orc_surface_options;
+
+/*
+ * Render the first surface along each ray: the first coarse lattice sample
+ * whose value lies in [iso_lo, iso_hi], refined towards the window boundary
+ * by `refine` halving steps, then shaded opaquely.  pix/n as orc_render.
+ * rgba[n*4]   (c, 1) on a surface hit, 0 otherwise
+ * t_hit       NULL or [n]: ray parameter of the refined hit, +inf without one
+ * k_hit       NULL or [n]: coarse index of the first sample in the window, -1
+ * flags       NULL or [n]: ORC_FLAG_HIT | ORC_FLAG_LATTICE_TIE (the hit is the
+ *             last lattice sample of a tie) | ORC_FLAG_ISO_NEAR
+ * Returns 0, or -1 on bad arguments.
+ */
+int orc_render_surface(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
+                       const orc_shading* sh, const orc_surface_options* opt, const long* pix,
+                       long n, double* rgba, double* t_hit, int* k_hit, int* flags, int threads);
 
 #ifdef __cplusplus
 }

@@ -228,3 +228,63 @@ def render(vol_zyx, spacing, vmin, vmax, tf, cam, sh, opt, pixels=None, n_overri
             A = A * (1.0 - a) + a
         out.append(np.concatenate([C, [A]]))
     return np.array(out).reshape(-1, 4)
+
+
+# ---------------------------------------------------------------- first-hit surface
+def render_surface(vol_zyx, spacing, vmin, vmax, tf, cam, sh, opt, pixels=None):
+    """(rgba [n,4], t_hit [n]) of the first-hit surface mode, written as an
+    interval bisection: the last coarse interval [t_{k-1}, t_k] is halved
+    refine-1 times by the window test at its midpoint, and the hit is the
+    midpoint of what is left (refine = 0 keeps t_k; a ray that starts inside
+    the window keeps t_in)."""
+    g = Grid(vol_zyx, spacing, vmin, vmax)
+    tf = np.asarray(tf, dtype=np.float64)
+    M = tf.shape[0]
+    ent = np.arange(M, dtype=np.float64)
+    W, H = cam["width"], cam["height"]
+    ext = (np.array([g.nx, g.ny, g.nz]) - 1) * g.s
+    lo_b = np.maximum(np.asarray(opt["clip_lo"]), 0.0)
+    hi_b = np.minimum(np.asarray(opt["clip_hi"]), ext)
+    ids = range(W * H) if pixels is None else pixels
+    step = opt["step"]
+
+    def value(o, d, t):
+        return g.sample((o + t * d) / g.s)
+
+    def inside(val):
+        return opt["iso_lo"] <= val <= opt["iso_hi"]
+
+    out, th = [], []
+    for pid in ids:
+        px, py = pid % W, pid // W
+        o, d = pixel_ray(cam, px, py)
+        span = box_span(o, d, lo_b, hi_b) if np.all(lo_b <= hi_b) else None
+        n = 0 if span is None else int(math.floor((span[1] - span[0]) / step)) + 1
+        hit = next((k for k in range(n) if inside(value(o, d, span[0] + k * step))), None)
+        if hit is None:
+            out.append(np.zeros(4))
+            th.append(math.inf)
+            continue
+        t_k = span[0] + hit * step
+        if hit == 0 or opt["refine"] == 0:
+            t = t_k
+        else:
+            a, b = t_k - step, t_k
+            for _ in range(opt["refine"] - 1):
+                m = 0.5 * (a + b)
+                if inside(value(o, d, m)):
+                    b = m
+                else:
+                    a = m
+            t = 0.5 * (a + b)
+        pw = o + t * d
+        pv = pw / g.s
+        val = g.sample(pv)
+        u = min(max((val - vmin) / (vmax - vmin), 0.0), 1.0) * (M - 1)
+        rgb = np.array([np.interp(u, ent, tf[:, c]) for c in range(3)])
+        if sh["model"] != "none":
+            grad, _ = g.gradient(opt["gradient_op"], pv)
+            rgb = shade(sh, rgb, grad, pw, d)
+        out.append(np.concatenate([rgb, [1.0]]))
+        th.append(t)
+    return np.array(out).reshape(-1, 4), np.array(th)

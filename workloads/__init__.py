@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "Scene", "blob_volume", "phantom_volume", "tf_ramps", "orbit_camera",
-    "default_shading", "default_options", "value_range",
+    "default_shading", "default_options", "default_surface_options", "value_range",
     "config_c1", "config_c2", "config_c3", "config_c4", "config_c5",
     "config_small",
 ]
@@ -241,6 +241,17 @@ def default_options(step=0.5, gradient_op="central", ert_threshold=0.0, skip_emp
     return {"step": float(step), "gradient_op": gradient_op, "ert_threshold": float(ert_threshold),
             "skip_empty": bool(skip_empty), "clip_lo": tuple(float(v) for v in clip_lo),
             "clip_hi": tuple(float(v) for v in clip_hi)}
+
+
+def default_surface_options(step=2.0, gradient_op="central", iso_lo=0.0, iso_hi=1e30, refine=6,
+                            skip_empty=False, clip_lo=(-1e30, -1e30, -1e30),
+                            clip_hi=(1e30, 1e30, 1e30)):
+    """First-hit surface mode: a raw-value window, a coarse step (the
+    hitpoint-refinement section allows 4-5x the volume-mode step) and the
+    number of refinement halvings (5 to 6 in the paper)."""
+    return {"step": float(step), "gradient_op": gradient_op, "iso_lo": float(iso_lo),
+            "iso_hi": float(iso_hi), "refine": int(refine), "skip_empty": bool(skip_empty),
+            "clip_lo": tuple(float(v) for v in clip_lo), "clip_hi": tuple(float(v) for v in clip_hi)}
 
 
 # --------------------------------------------------------------------------
