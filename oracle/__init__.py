@@ -53,7 +53,8 @@ class _Shading(C.Structure):
 
 class _Options(C.Structure):
     _fields_ = [("step", C.c_double), ("gradient_op", C.c_int), ("ert_threshold", C.c_double),
-                ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3)]
+                ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3), ("nearest", C.c_int),
+                ("ref_step", C.c_double)]
 
 
 class _SurfaceOptions(C.Structure):
@@ -74,6 +75,8 @@ def lib():
         dp, ip, lp = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_long)
         L.orc_sample.restype = C.c_double
         L.orc_sample.argtypes = [C.POINTER(_Volume), dp]
+        L.orc_sample_nearest.restype = C.c_double
+        L.orc_sample_nearest.argtypes = [C.POINTER(_Volume), dp]
         L.orc_gradient.restype = None
         L.orc_gradient.argtypes = [C.POINTER(_Volume), C.c_int, dp, dp, dp]
         L.orc_tf.restype = None
@@ -127,12 +130,18 @@ def _shading(sh):
 
 def _options(opt):
     return _Options(opt["step"], OP[opt["gradient_op"]], opt["ert_threshold"],
-                    (C.c_double * 3)(*opt["clip_lo"]), (C.c_double * 3)(*opt["clip_hi"]))
+                    (C.c_double * 3)(*opt["clip_lo"]), (C.c_double * 3)(*opt["clip_hi"]),
+                    int(bool(opt.get("nearest", False))), float(opt.get("ref_step", 0.0)))
 
 
 def sample(vol: Volume, p):
     p = np.ascontiguousarray(p, dtype=np.float64)
     return lib().orc_sample(C.byref(vol.s), _dp(p))
+
+
+def sample_nearest(vol: Volume, p):
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    return lib().orc_sample_nearest(C.byref(vol.s), _dp(p))
 
 
 def gradient(vol: Volume, op: str, p):

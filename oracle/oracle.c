@@ -71,6 +71,12 @@ double orc_sample(const orc_volume* v, const double p[3]) {
     return lerp(I5, I6, tz);
 }
 
+/* Section 3.3: the simplest sampling rounds the coordinates to whole
+ * voxels.  Reading: round half up, floor(p + 1/2), then the edge clamp. */
+double orc_sample_nearest(const orc_volume* v, const double p[3]) {
+    return voxel(v, (long)floor(p[0] + 0.5), (long)floor(p[1] + 0.5), (long)floor(p[2] + 0.5));
+}
+
 /* ------------------------------------------------------------------ */
 /* Section 3.5: gradient operators.                                    */
 /*                                                                     */
@@ -313,7 +319,8 @@ typedef struct {
     double pv[3];       /* voxel-space position */
     double val, u;
     int interior;       /* 0 < normalised value < 1 */
-    double rgba[4];     /* TF output */
+    double rgba[4];     /* TF output (alpha after opacity correction) */
+    double alpha_tf;    /* TF alpha before opacity correction */
     double c[3];        /* shaded colour */
 } sample_state;
 
@@ -325,18 +332,31 @@ static void eval_sample(const orc_volume* v, const double* tf, int M, const orc_
         pw[a] = rs->o[a] + t * rs->d[a];
         s->pv[a] = pw[a] / v->spacing[a];
     }
-    s->val = orc_sample(v, s->pv);
+    /* nearest sampling: the value and the gradient taps are taken at the
+     * rounded point, so the operator's stencil sits on one voxel */
+    double pr[3];
+    for (int a = 0; a < 3; ++a) pr[a] = opt->nearest ? floor(s->pv[a] + 0.5) : s->pv[a];
+    s->val = opt->nearest ? orc_sample_nearest(v, s->pv) : orc_sample(v, s->pv);
     s->u = value_to_u(v, s->val, M, &s->interior);
     orc_tf(tf, M, s->u, s->rgba);
+    s->alpha_tf = s->rgba[3];
+    if (opt->ref_step > 0.0)
+        s->rgba[3] = 1.0 - pow(1.0 - s->rgba[3], opt->step / opt->ref_step);
     if (sh->model == ORC_SHADE_NONE || s->rgba[3] == 0.0) {
         /* no light needed: empty samples get no colour (Section 3.5) */
         s->c[0] = s->rgba[0]; s->c[1] = s->rgba[1]; s->c[2] = s->rgba[2];
         return;
     }
     double g[3];
-    orc_gradient(v, opt->gradient_op, s->pv, g, NULL);
+    orc_gradient(v, opt->gradient_op, pr, g, NULL);
     orc_shade(sh, s->rgba, g, pw, rs->d, s->c);
 }
+
+/* Opacity correction (not in the paper, which is silent on the step
+ * dependence of a): with ref_step > 0 the table opacity is taken as
+ * defined for a sample distance ref_step and converted to the step in use,
+ * a = 1 - (1 - a_tf)^(step/ref_step), so that a slab of constant a_tf has
+ * the same opacity at every step.  Off (ref_step = 0) by default. */
 
 /* Section 3.9, eq. (6) composites back to front: C_out = C_in (1 - a) + C a.
  * Evaluated front to back with the transmittance T = prod (1 - a_j) of the
@@ -371,6 +391,7 @@ static int check_args(const orc_volume* v, const orc_camera* cam, const double* 
     if (!v || !v->data || !cam || !tf || !opt) return -1;
     if (v->nx < 1 || v->ny < 1 || v->nz < 1 || M < 2) return -1;
     if (!(opt->step > 0.0) || !(v->vmax > v->vmin)) return -1;
+    if (!(opt->ref_step >= 0.0) || isinf(opt->ref_step)) return -1;
     if (cam->width < 1 || cam->height < 1) return -1;
     return 0;
 }
@@ -462,6 +483,13 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
                 da += g[ch] * (s->c[ch] - B[ch]);
             }
             da = Tk[k] * (da + g[3] * P);
+            /* opacity correction a = 1 - (1 - a_tf)^e: da/da_tf = e (1 - a_tf)^(e-1),
+             * taken as 0 at a_tf = 1 when e < 1 (not differentiable there) */
+            if (opt->ref_step > 0.0) {
+                double e = opt->step / opt->ref_step;
+                double om = 1.0 - s->alpha_tf;
+                da *= (om > 0.0 || e >= 1.0) ? e * pow(om, e - 1.0) : 0.0;
+            }
             /* TF entries i, i1 with weights (1-t, t) -- orc_tf's lerp */
             double fi = floor(s->u);
             long i = (long)fi;
@@ -476,7 +504,13 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
                 dtf[i1 * 4 + ch] += t * dgrad[ch];
                 du += dgrad[ch] * (tf[i1 * 4 + ch] - tf[i * 4 + ch]);
             }
-            if (s->interior) {
+            if (s->interior && opt->nearest) {
+                double dval = du * (double)(M - 1) / (v->vmax - v->vmin);
+                long ii = clampl((long)floor(s->pv[0] + 0.5), v->nx),
+                     jj = clampl((long)floor(s->pv[1] + 0.5), v->ny),
+                     kk = clampl((long)floor(s->pv[2] + 0.5), v->nz);
+                dvol[(kk * (long)v->ny + jj) * (long)v->nx + ii] += dval;
+            } else if (s->interior) {
                 double dval = du * (double)(M - 1) / (v->vmax - v->vmin);
                 double fx0 = floor(s->pv[0]), fy0 = floor(s->pv[1]), fz0 = floor(s->pv[2]);
                 double tx = s->pv[0] - fx0, ty = s->pv[1] - fy0, tz = s->pv[2] - fz0;

@@ -78,10 +78,14 @@ typedef struct {
     int gradient_op;         /* ORC_OP_* */
     double ert_threshold;    /* 0: off, else stop once 1-T >= threshold */
     double clip_lo[3], clip_hi[3]; /* clip box in world units, intersected with the volume box */
+    int nearest;             /* 1: nearest-voxel sampling (Section 3.3's rounding) */
+    double ref_step;         /* > 0: opacity correction to this reference step; 0: off */
 } orc_options;
 
 /* trilinear sample at a voxel-space point (Section 3.4) */
 double orc_sample(const orc_volume* v, const double p[3]);
+/* nearest-voxel sample: the voxel at floor(p + 1/2) per axis (Section 3.3) */
+double orc_sample_nearest(const orc_volume* v, const double p[3]);
 /* gradient estimate at a voxel-space point (Section 3.5), scaled to
  * normalised value per world unit; raw = stencil sum before scaling */
 void orc_gradient(const orc_volume* v, int op, const double p[3], double g[3], double raw[3]);

@@ -195,15 +195,28 @@ def render(vol_zyx, spacing, vmin, vmax, tf, cam, sh, opt, pixels=None, n_overri
         else:
             n = 0 if span is None else int(math.floor((span[1] - span[0]) / opt["step"])) + 1
         alphas, cols = [], []
+        nearest = opt.get("nearest", False)
+        ref = opt.get("ref_step", 0.0)
         for k in range(n):
             t = span[0] + k * opt["step"]
             pw = o + t * d
             pv = pw / g.s
-            val = g.sample(pv)
+            if nearest:
+                idx = [int(math.floor(c + 0.5)) for c in pv]
+                val = g.at(*idx)
+            else:
+                val = g.sample(pv)
             u = min(max((val - vmin) / (vmax - vmin), 0.0), 1.0) * (M - 1)
             rgba = np.array([np.interp(u, ent, tf[:, c]) for c in range(4)])
+            if ref > 0 and rgba[3] < 1.0:
+                # the same opacity per unit length: -log(1-a) scales with the step
+                rgba[3] = -math.expm1(math.log1p(-rgba[3]) * opt["step"] / ref)
             if sh["model"] != "none" and rgba[3] != 0.0:
-                grad, _ = g.gradient(opt["gradient_op"], pv)
+                if nearest:
+                    raw = g.stencil(masks(opt["gradient_op"]), *idx)
+                    grad = raw / gain(opt["gradient_op"]) / g.s / (g.vmax - g.vmin)
+                else:
+                    grad, _ = g.gradient(opt["gradient_op"], pv)
                 col = shade(sh, rgba, grad, pw, d)
             else:
                 col = rgba[:3]

@@ -7,9 +7,10 @@ import pytest
 import workloads as W
 
 
-def _scene(seed, ert=0.0):
+def _scene(seed, ert=0.0, nearest=False, ref_step=0.0):
     sc = W.config_small(seed=seed, dims=(7, 6, 8), dtype=np.float32, image=(9, 8),
                         shading="none", ert=ert)
+    sc.options.update(nearest=nearest, ref_step=ref_step)
     return sc
 
 
@@ -19,11 +20,16 @@ def _loss(orc, vol_arr, sc, tf, g):
     return float((r["rgba"] * g).sum())
 
 
-@pytest.mark.parametrize("seed,ert", [(21, 0.0), (22, 0.0), (23, 0.8)])
-def test_grad_tf_matches_fd(orc, seed, ert):
+VARIANTS = [dict(), dict(nearest=True), dict(ref_step=0.8), dict(nearest=True, ref_step=0.3)]
+
+
+@pytest.mark.parametrize("seed,ert,var", [(21, 0.0, 0), (22, 0.0, 0), (23, 0.8, 0), (26, 0.0, 1),
+                                          (27, 0.0, 2), (28, 0.7, 3)])
+def test_grad_tf_matches_fd(orc, seed, ert, var):
     """dL/dTF: C is linear in the rgb entries, so their FD is exact up to
-    rounding; the alpha entries are smooth away from ERT decisions."""
-    sc = _scene(seed, ert)
+    rounding; the alpha entries are smooth away from ERT decisions.  Also
+    with nearest sampling and with opacity correction."""
+    sc = _scene(seed, ert, **VARIANTS[var])
     rng = np.random.default_rng(seed)
     H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
     g = rng.normal(size=(H, Wd, 4))
@@ -42,9 +48,9 @@ def test_grad_tf_matches_fd(orc, seed, ert):
             assert abs(fd - dtf[i, ch]) <= 1e-6 * max(1.0, abs(fd)), (i, ch, fd, dtf[i, ch])
 
 
-@pytest.mark.parametrize("seed", [24, 25])
-def test_grad_volume_matches_fd(orc, seed):
-    sc = _scene(seed)
+@pytest.mark.parametrize("seed,var", [(24, 0), (25, 0), (29, 1), (30, 2), (31, 3)])
+def test_grad_volume_matches_fd(orc, seed, var):
+    sc = _scene(seed, **VARIANTS[var])
     rng = np.random.default_rng(seed)
     H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
     g = rng.normal(size=(H, Wd, 4))
