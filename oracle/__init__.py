@@ -93,7 +93,8 @@ def lib():
                                  dp, dp, ip, ip, dp, C.c_int]
         L.orc_render_grad.restype = C.c_int
         L.orc_render_grad.argtypes = [C.POINTER(_Volume), C.POINTER(_Camera), dp, C.c_int,
-                                      C.POINTER(_Options), lp, C.c_long, dp, dp, dp]
+                                      C.POINTER(_Shading), C.POINTER(_Options), lp, C.c_long,
+                                      dp, dp, dp]
         L.orc_render_surface.restype = C.c_int
         L.orc_render_surface.argtypes = [C.POINTER(_Volume), C.POINTER(_Camera), dp, C.c_int,
                                          C.POINTER(_Shading), C.POINTER(_SurfaceOptions), lp,
@@ -210,10 +211,11 @@ def render(vol: Volume, cam, tf, shading, options, pixels=None, threads=0):
     return out
 
 
-def render_grad(vol: Volume, cam, tf, options, g_rgba, pixels=None):
-    """dL/dvolume [nz,ny,nx] and dL/dTF [M,4] for shading NONE."""
+def render_grad(vol: Volume, cam, tf, options, g_rgba, pixels=None, shading=None):
+    """dL/dvolume [nz,ny,nx] and dL/dTF [M,4]; shading None means NONE."""
     L = lib()
     c, o = _camera(cam), _options(options)
+    s = C.byref(_shading(shading)) if shading is not None else None
     t = np.ascontiguousarray(tf, dtype=np.float64)
     g = np.ascontiguousarray(g_rgba, dtype=np.float64).reshape(-1, 4)
     if pixels is None:
@@ -224,8 +226,8 @@ def render_grad(vol: Volume, cam, tf, options, g_rgba, pixels=None):
     assert g.shape[0] == n
     dvol = np.zeros(vol.data.shape)
     dtf = np.zeros(t.shape)
-    rc = L.orc_render_grad(C.byref(vol.s), C.byref(c), _dp(t), t.shape[0], C.byref(o), pix_p, n,
-                           _dp(g), _dp(dvol), _dp(dtf))
+    rc = L.orc_render_grad(C.byref(vol.s), C.byref(c), _dp(t), t.shape[0], s, C.byref(o), pix_p,
+                           n, _dp(g), _dp(dvol), _dp(dtf))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return dvol, dtf

@@ -316,6 +316,7 @@ static void setup_ray(const orc_volume* v, const orc_camera* cam, const orc_opti
 
 /* one lattice sample: value, TF colour, gradient and shaded colour */
 typedef struct {
+    double pw[3];       /* world position */
     double pv[3];       /* voxel-space position */
     double val, u;
     int interior;       /* 0 < normalised value < 1 */
@@ -327,7 +328,7 @@ typedef struct {
 static void eval_sample(const orc_volume* v, const double* tf, int M, const orc_shading* sh,
                         const orc_options* opt, const ray_setup* rs, long k, sample_state* s) {
     double t = rs->t_in + (double)k * opt->step;
-    double pw[3];
+    double* pw = s->pw;
     for (int a = 0; a < 3; ++a) {
         pw[a] = rs->o[a] + t * rs->d[a];
         s->pv[a] = pw[a] / v->spacing[a];
@@ -443,13 +444,106 @@ int orc_render(const orc_volume* v, const orc_camera* cam, const double* tf, int
 /* continues through the TF interpolation to u, through the clamp to    */
 /* the value, and through the trilinear weights to the 8 voxels.        */
 /* ------------------------------------------------------------------ */
+/* Trilinear weights of p (Section 3.4) scattered: dvol[corner] += w * s. */
+static void scatter_trilinear(const orc_volume* v, const double p[3], double s, double* dvol) {
+    double fx0 = floor(p[0]), fy0 = floor(p[1]), fz0 = floor(p[2]);
+    double tx = p[0] - fx0, ty = p[1] - fy0, tz = p[2] - fz0;
+    for (int c = 0; c < 8; ++c) {
+        int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+        double w = (cx ? tx : 1 - tx) * (cy ? ty : 1 - ty) * (cz ? tz : 1 - tz);
+        long ii = clampl((long)fx0 + cx, v->nx), jj = clampl((long)fy0 + cy, v->ny),
+             kk = clampl((long)fz0 + cz, v->nz);
+        dvol[(kk * (long)v->ny + jj) * (long)v->nx + ii] += w * s;
+    }
+}
+
+/* Reverse of orc_gradient: every tap is a trilinear sample at p + offset,
+ * so dL/dG_a scatters through each tap's trilinear weights, scaled like
+ * the forward (mask weight / gain / spacing / value range). */
+static void gradient_adjoint(const orc_volume* v, int op, const double p[3], const double dg[3],
+                             double* dvol) {
+    for (int a = 0; a < 3; ++a) {
+        if (dg[a] == 0.0) continue;
+        double s = dg[a] / op_gain(op) / v->spacing[a] / (v->vmax - v->vmin);
+        int beta = (a + 1) % 3, gamma = (a + 2) % 3;
+        for (int b = -1; b <= 1; ++b)
+            for (int c = -1; c <= 1; ++c) {
+                if (op == ORC_OP_CENTRAL && (b != 0 || c != 0)) continue;
+                double w = op == ORC_OP_CENTRAL ? 1.0 : mask_weight(op, b, c);
+                double q1[3] = {p[0], p[1], p[2]}, q0[3];
+                q1[beta] += b;
+                q1[gamma] += c;
+                memcpy(q0, q1, sizeof q0);
+                q1[a] += 1.0;
+                q0[a] -= 1.0;
+                scatter_trilinear(v, q1, w * s, dvol);
+                scatter_trilinear(v, q0, -w * s, dvol);
+            }
+    }
+}
+
+/* Reverse of orc_shade: given dL/dc, dL/drgb and dL/dG.  At the kinks
+ * (max(0, .), the |G| floor) the derivative of the branch the forward took
+ * is used. */
+static void shade_adjoint(const orc_shading* sh, const double rgb[3], const double g[3],
+                          const double p_world[3], const double d[3], const double dc[3],
+                          double drgb[3], double dg[3]) {
+    dg[0] = dg[1] = dg[2] = 0.0;
+    if (sh->model == ORC_SHADE_NONE) {
+        for (int ch = 0; ch < 3; ++ch) drgb[ch] = dc[ch];
+        return;
+    }
+    double gn = sqrt(dot3(g, g));
+    double den = gn > sh->grad_eps ? gn : sh->grad_eps;
+    double ghat[3] = {g[0] / den, g[1] / den, g[2] / den};
+    double L[3], tmp[3], dghat[3];
+    if (sh->light_is_point) {
+        for (int a = 0; a < 3; ++a) tmp[a] = sh->light[a] - p_world[a];
+        normalize3(tmp, L);
+    } else {
+        normalize3(sh->light, L);
+    }
+    double dc_rgb = dc[0] * rgb[0] + dc[1] * rgb[1] + dc[2] * rgb[2];
+    if (sh->model == ORC_SHADE_PAPER_LAMBERT) {
+        /* c = rgb (L . ghat) */
+        double illum = dot3(L, ghat);
+        for (int ch = 0; ch < 3; ++ch) drgb[ch] = dc[ch] * illum;
+        for (int a = 0; a < 3; ++a) dghat[a] = dc_rgb * L[a];
+    } else {
+        /* c = rgb (ka + kd max(0, N.L)) + ks max(0, N.H)^s, N = -ghat */
+        double N[3] = {-ghat[0], -ghat[1], -ghat[2]}, Hh[3];
+        for (int a = 0; a < 3; ++a) tmp[a] = L[a] - d[a];
+        normalize3(tmp, Hh);
+        double nl = dot3(N, L), nh = dot3(N, Hh);
+        double K = sh->ka + sh->kd * (nl > 0.0 ? nl : 0.0);
+        for (int ch = 0; ch < 3; ++ch) drgb[ch] = dc[ch] * K;
+        double dN[3] = {0.0, 0.0, 0.0};
+        if (nl > 0.0)
+            for (int a = 0; a < 3; ++a) dN[a] += sh->kd * dc_rgb * L[a];
+        if (nh > 0.0 && sh->shininess != 0.0) {
+            double ds = sh->ks * (dc[0] + dc[1] + dc[2]) * sh->shininess *
+                        pow(nh, sh->shininess - 1.0);
+            for (int a = 0; a < 3; ++a) dN[a] += ds * Hh[a];
+        }
+        for (int a = 0; a < 3; ++a) dghat[a] = -dN[a];
+    }
+    /* ghat = g / max(|g|, eps) */
+    if (gn > sh->grad_eps) {
+        double proj = dot3(ghat, dghat);
+        for (int a = 0; a < 3; ++a) dg[a] = (dghat[a] - ghat[a] * proj) / gn;
+    } else {
+        for (int a = 0; a < 3; ++a) dg[a] = dghat[a] / sh->grad_eps;
+    }
+}
+
 int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
-                    const orc_options* opt, const long* pix, long n, const double* g_rgba,
-                    double* dvol, double* dtf) {
+                    const orc_shading* sh_in, const orc_options* opt, const long* pix, long n,
+                    const double* g_rgba, double* dvol, double* dtf) {
     if (check_args(v, cam, tf, M, opt) || !g_rgba || !dvol || !dtf) return -1;
     orc_shading none;
     memset(&none, 0, sizeof none);
     none.model = ORC_SHADE_NONE;
+    const orc_shading* sh = sh_in ? sh_in : &none;
     long total = (long)cam->width * cam->height;
     if (!pix) n = total;
     for (long q = 0; q < n; ++q) {
@@ -466,7 +560,7 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
         double T = 1.0;
         long last = -1;
         for (long k = 0; k <= rs.K; ++k) {
-            eval_sample(v, tf, M, &none, opt, &rs, k, &S[k]);
+            eval_sample(v, tf, M, sh, opt, &rs, k, &S[k]);
             Tk[k] = T;
             T *= (1.0 - S[k].rgba[3]);
             last = k;
@@ -477,10 +571,22 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
         for (long k = last; k >= 0; --k) {
             const sample_state* s = &S[k];
             double a = s->rgba[3];
+            double pr[3];
+            for (int ax = 0; ax < 3; ++ax)
+                pr[ax] = opt->nearest ? floor(s->pv[ax] + 0.5) : s->pv[ax];
+            /* the lit colour; the forward skips the lighting where a = 0 (the
+             * colour is multiplied by 0 there), but dC/da needs it at a = 0 too */
+            double G[3] = {0.0, 0.0, 0.0}, c_lit[3];
+            if (sh->model != ORC_SHADE_NONE) {
+                orc_gradient(v, opt->gradient_op, pr, G, NULL);
+                orc_shade(sh, s->rgba, G, s->pw, rs.d, c_lit);
+            } else {
+                c_lit[0] = s->c[0]; c_lit[1] = s->c[1]; c_lit[2] = s->c[2];
+            }
             double dc[3], da = 0.0;
             for (int ch = 0; ch < 3; ++ch) {
                 dc[ch] = g[ch] * Tk[k] * a;
-                da += g[ch] * (s->c[ch] - B[ch]);
+                da += g[ch] * (c_lit[ch] - B[ch]);
             }
             da = Tk[k] * (da + g[3] * P);
             /* opacity correction a = 1 - (1 - a_tf)^e: da/da_tf = e (1 - a_tf)^(e-1),
@@ -497,31 +603,22 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
             if (i > M - 1) i = M - 1;
             long i1 = i + 1 < M ? i + 1 : M - 1;
             double t = s->u - (double)i;
-            double dgrad[4] = {dc[0], dc[1], dc[2], da};
+            /* lighting (Section 3.8): dL/dc -> dL/d(table rgb) and dL/dG */
+            double drgb[3] = {dc[0], dc[1], dc[2]}, dG[3] = {0.0, 0.0, 0.0};
+            if (sh->model != ORC_SHADE_NONE && a != 0.0)
+                shade_adjoint(sh, s->rgba, G, s->pw, rs.d, dc, drgb, dG);
+            double dgrad[4] = {drgb[0], drgb[1], drgb[2], da};
             double du = 0.0;
             for (int ch = 0; ch < 4; ++ch) {
                 dtf[i * 4 + ch] += (1.0 - t) * dgrad[ch];
                 dtf[i1 * 4 + ch] += t * dgrad[ch];
                 du += dgrad[ch] * (tf[i1 * 4 + ch] - tf[i * 4 + ch]);
             }
-            if (s->interior && opt->nearest) {
-                double dval = du * (double)(M - 1) / (v->vmax - v->vmin);
-                long ii = clampl((long)floor(s->pv[0] + 0.5), v->nx),
-                     jj = clampl((long)floor(s->pv[1] + 0.5), v->ny),
-                     kk = clampl((long)floor(s->pv[2] + 0.5), v->nz);
-                dvol[(kk * (long)v->ny + jj) * (long)v->nx + ii] += dval;
-            } else if (s->interior) {
-                double dval = du * (double)(M - 1) / (v->vmax - v->vmin);
-                double fx0 = floor(s->pv[0]), fy0 = floor(s->pv[1]), fz0 = floor(s->pv[2]);
-                double tx = s->pv[0] - fx0, ty = s->pv[1] - fy0, tz = s->pv[2] - fz0;
-                for (int c = 0; c < 8; ++c) {
-                    int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
-                    double w = (cx ? tx : 1 - tx) * (cy ? ty : 1 - ty) * (cz ? tz : 1 - tz);
-                    long ii = clampl((long)fx0 + cx, v->nx), jj = clampl((long)fy0 + cy, v->ny),
-                         kk = clampl((long)fz0 + cz, v->nz);
-                    dvol[(kk * (long)v->ny + jj) * (long)v->nx + ii] += w * dval;
-                }
-            }
+            /* the value: through the clamp to the trilinear (or nearest) weights */
+            if (s->interior)
+                scatter_trilinear(v, pr, du * (double)(M - 1) / (v->vmax - v->vmin), dvol);
+            /* the gradient operator's taps */
+            gradient_adjoint(v, opt->gradient_op, pr, dG, dvol);
             for (int ch = 0; ch < 3; ++ch) B[ch] = a * s->c[ch] + (1.0 - a) * B[ch];
             P *= (1.0 - a);
         }

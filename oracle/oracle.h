@@ -117,14 +117,16 @@ int orc_render(const orc_volume* v, const orc_camera* cam, const double* tf, int
                int threads);
 
 /*
- * Reverse mode of orc_render for shading NONE.  g_rgba[n*4] = dL/d(rgba)
- * of the listed pixels.  dvol[nz*ny*nx] and dtf[M*4] are accumulated (+=).
- * Uses the same lattice (primary sample count) and the same early ray
- * termination as orc_render.  Returns 0, or -1 on bad arguments.
+ * Reverse mode of orc_render.  sh = NULL means shading NONE; with a shading
+ * model the chain also runs through the lighting, the normalisation and the
+ * gradient operator's taps.  g_rgba[n*4] = dL/d(rgba) of the listed pixels.
+ * dvol[nz*ny*nx] and dtf[M*4] are accumulated (+=).  Uses the same lattice
+ * (primary sample count) and the same early ray termination as orc_render.
+ * Returns 0, or -1 on bad arguments.
  */
 int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
-                    const orc_options* opt, const long* pix, long n, const double* g_rgba,
-                    double* dvol, double* dtf);
+                    const orc_shading* sh, const orc_options* opt, const long* pix, long n,
+                    const double* g_rgba, double* dvol, double* dtf);
 
 /* First-hit surface mode (Sections 3, 3.11 and 5.1). */
 typedef struct {

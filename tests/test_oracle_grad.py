@@ -75,3 +75,77 @@ def test_grad_volume_matches_fd(orc, seed, var):
         checked += 1
         assert abs(fd - dvol[k, j, i]) <= 1e-5 * max(1.0, abs(fd)), (idx, fd, dvol[k, j, i])
     assert checked >= 10
+
+
+SHADED = [("blinn_phong", "central", False), ("blinn_phong", "sobel3d", False),
+          ("paper_lambert", "zucker_hummel", False), ("blinn_phong", "zucker_hummel", True),
+          ("paper_lambert", "central", True)]
+
+
+def _shaded_scene(seed, model, op, nearest):
+    sc = W.config_small(seed=seed, dims=(7, 6, 8), dtype=np.float32, image=(9, 8), op=op,
+                        shading=model, ert=0.0)
+    if model == "paper_lambert":
+        sc.shading["light_is_point"] = True
+        sc.shading["light"] = (14.0, -9.0, 11.0)
+    sc.options.update(nearest=nearest)
+    return sc
+
+
+def _loss_sh(orc, vol_arr, sc, tf, g):
+    v = orc.Volume(vol_arr, sc.spacing, sc.vmin, sc.vmax)
+    r = orc.render(v, sc.cameras[0], tf, sc.shading, sc.options)
+    return float((r["rgba"] * g).sum())
+
+
+@pytest.mark.parametrize("model,op,nearest", SHADED)
+def test_shaded_grad_volume_matches_fd(orc, model, op, nearest):
+    """Reverse mode through the lighting, the |G| normalisation and the
+    gradient operator's taps vs central differences of the forward."""
+    seed = 40 + SHADED.index((model, op, nearest))
+    sc = _shaded_scene(seed, model, op, nearest)
+    rng = np.random.default_rng(seed)
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    g = rng.normal(size=(H, Wd, 4))
+    vol = sc.volume.astype(np.float64)
+    v = orc.Volume(vol, sc.spacing, sc.vmin, sc.vmax)
+    dvol, _ = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, g, shading=sc.shading)
+    cand = np.argwhere(np.abs(dvol) > 1e-6)
+    assert len(cand) > 10
+    h = 1e-6
+    checked = 0
+    for idx in cand[rng.choice(len(cand), size=min(30, len(cand)), replace=False)]:
+        k, j, i = idx
+        vp, vm = vol.copy(), vol.copy()
+        vp[k, j, i] += h
+        vm[k, j, i] -= h
+        l0 = _loss_sh(orc, vol, sc, sc.tf, g)
+        lp, lm = _loss_sh(orc, vp, sc, sc.tf, g), _loss_sh(orc, vm, sc, sc.tf, g)
+        fd, fl, fr = (lp - lm) / (2 * h), (l0 - lm) / h, (lp - l0) / h
+        if abs(fl - fr) > 1e-4 * max(1.0, abs(fd)):
+            continue                      # a kink (TF breakpoint, max(0,.)) inside [v-h, v+h]
+        checked += 1
+        assert abs(fd - dvol[k, j, i]) <= 1e-5 * max(1.0, abs(fd)), (idx, fd, dvol[k, j, i])
+    assert checked >= 10
+
+
+@pytest.mark.parametrize("model,op,nearest", SHADED[:3])
+def test_shaded_grad_tf_matches_fd(orc, model, op, nearest):
+    seed = 50 + SHADED.index((model, op, nearest))
+    sc = _shaded_scene(seed, model, op, nearest)
+    rng = np.random.default_rng(seed)
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    g = rng.normal(size=(H, Wd, 4))
+    v = orc.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
+    _, dtf = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, g, shading=sc.shading)
+    tf = sc.tf.astype(np.float64)
+    used = np.argwhere(np.abs(dtf).sum(1) > 0)[:, 0]
+    assert used.size > 5
+    h = 1e-6
+    for i in rng.choice(used, size=min(10, used.size), replace=False):
+        for ch in range(4):
+            tp, tm = tf.copy(), tf.copy()
+            tp[i, ch] += h
+            tm[i, ch] -= h
+            fd = (_loss_sh(orc, sc.volume, sc, tp, g) - _loss_sh(orc, sc.volume, sc, tm, g)) / (2 * h)
+            assert abs(fd - dtf[i, ch]) <= 1e-6 * max(1.0, abs(fd)), (i, ch, fd, dtf[i, ch])
