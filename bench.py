@@ -286,6 +286,39 @@ def run_c4(args):
     }
 
 
+def run_surface(args, sc=None, vol=None, tf=None):
+    """First-hit surface mode over the headline orbit: coarse step 2.0 (4x
+    the volume-mode step, as hitpoint refinement allows), 6 refinement
+    steps, window [500, 4095], Sobel3D Blinn-Phong, brick skipping."""
+    if sc is None:
+        sc = W.config_c3(n_views=args.views)
+        vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+        rc.rc_build_bricks(vol, 8)
+        tf = to_dev(sc.tf)
+    opt = W.default_surface_options(step=2.0, gradient_op="sobel3d", iso_lo=500.0, iso_hi=4095.0,
+                                    refine=6, skip_empty=True)
+    cam0 = sc.cameras[0]
+    out = torch.empty((cam0["height"], cam0["width"], 4), dtype=torch.float32, device="cuda")
+    t_hit = torch.empty((cam0["height"], cam0["width"]), dtype=torch.float32, device="cuda")
+    for cam in sc.cameras[:2]:
+        rc.rc_render_surface(vol, cam, tf, sc.shading, opt, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for cam in sc.cameras:
+        rc.rc_render_surface(vol, cam, tf, sc.shading, opt, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / len(sc.cameras)
+    rc.rc_render_surface(vol, cam0, tf, sc.shading, opt, out=out, t_hit=t_hit)
+    hits = int(torch.isfinite(t_hit).sum().item())
+    return {"workload": "512^3 u16 phantom -> 1024^2, 36-view orbit, first-hit surface: window "
+                        "[500, 4095], coarse step 2.0, 6 refinement steps, Sobel3D Blinn-Phong, "
+                        "brick skipping",
+            "ms_per_view": round(ms, 4), "fps": round(1e3 / ms, 1),
+            "surface_pixels_view0": hits}
+
+
 def cpu_baseline(sc, counts_unused=None):
     """FP64 oracle on one full Sobel3D view of the headline workload."""
     import oracle
@@ -324,8 +357,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the differentiable form")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB copy first")
-    ap.add_argument("--only", choices=["c4", "c5"], default=None,
-                    help="run only the batched (c4) or differentiable (c5) form and print it")
+    ap.add_argument("--only", choices=["c4", "c5", "surface"], default=None,
+                    help="run only the batched (c4), differentiable (c5) or first-hit surface "
+                         "form and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -338,7 +372,8 @@ def main():
     if args.calib_copy:
         calib_copy()
     if args.only:
-        print(json.dumps(run_c4(args) if args.only == "c4" else run_c5(args)), flush=True)
+        fn = {"c4": run_c4, "c5": run_c5, "surface": run_surface}[args.only]
+        print(json.dumps(fn(args)), flush=True)
         return
 
     sc, vol, tf, ms_per_step, render_ms, counts = run_c3(args)
@@ -378,6 +413,8 @@ def main():
         result["differentiable"] = run_c5(args)
         log("bench: batched form")
         result["batched"] = run_c4(args)
+        log("bench: first-hit surface form")
+        result["surface"] = run_surface(args, sc, vol, tf)
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
         result["cpu_baseline"] = cpu_baseline(sc)

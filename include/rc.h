@@ -87,6 +87,10 @@ typedef struct {
     float grad_eps;           /* > 0: floor of |G| (normalised value per world unit) */
 } rc_shading;
 
+/* Section 3.3: coordinates rounded to whole voxels (the simplest scheme,
+ * round half up) or trilinear interpolation of the 8 surrounding voxels. */
+typedef enum { RC_SAMPLE_TRILINEAR = 0, RC_SAMPLE_NEAREST = 1 } rc_sampling;
+
 typedef struct {
     double step;              /* sample distance in world units, > 0 */
     double clip_lo[3];        /* clip box in world units, intersected with the volume box */
@@ -95,6 +99,10 @@ typedef struct {
     int32_t gradient_op;      /* rc_gradient_op */
     int32_t skip_empty;       /* 1: skip bricks whose samples all have alpha 0 (needs rc_build_bricks) */
     int32_t reserved;         /* must be 0 */
+    int32_t sampling;         /* rc_sampling; with NEAREST the value and the gradient stencil sit
+                                 on the voxel nearest to the sample point */
+    float opacity_ref_step;   /* 0: off; > 0: table opacities are per this sample distance and
+                                 are corrected to `step`: a = 1 - (1 - a_tf)^(step / ref) */
 } rc_options;
 
 /* Optional per-render counters, accumulated (+=) with device atomics. */
@@ -170,8 +178,13 @@ rc_status rc_render(const rc_volume* vol, const rc_camera* cam, const float* tf_
                     rc_aux* aux_dev, rc_stats* stats_dev, void* stream);
 
 /*
- * Reverse mode of rc_render for shading NONE (the renderer's output is then
- * differentiable in the voxels and the table almost everywhere).
+ * Reverse mode of rc_render (the output is differentiable in the voxels and
+ * the table almost everywhere; at the kinks -- table breakpoints, max(0, .)
+ * in the lighting, the |G| floor -- the derivative of the branch the forward
+ * took is used).  With a shading model the chain runs through the lighting,
+ * the normalisation and every tap of the gradient operator (up to 64 voxels
+ * per sample); where a sample's opacity is 0 its lit colour still enters
+ * dL/dalpha.
  *   aux_dev        the rc_aux written by the forward render with the same
  *                  volume contents, camera, table and options
  *   grad_rgba_dev  device [height][width][4] float32, dL/d(output)
@@ -180,8 +193,7 @@ rc_status rc_render(const rc_volume* vol, const rc_camera* cam, const float* tf_
  *   grad_tf_dev    device [tf_len][4] float32, accumulated (+=)
  * The march runs back to front from each ray's last sample and recovers the
  * transmittance from aux.t_final instead of storing per-sample state.
- * Errors: RC_E_INVALID, RC_E_UNSUPPORTED (shading model not NONE),
- * RC_E_DEVICE.
+ * Errors: RC_E_INVALID, RC_E_DEVICE.
  */
 rc_status rc_render_backward(const rc_volume* vol, const rc_camera* cam, const float* tf_rgba_dev,
                              int tf_len, const rc_shading* sh, const rc_options* opt,
@@ -264,7 +276,7 @@ rc_status rc_render_views(const rc_volume* vol, const rc_camera* cams, int n_vie
                           const rc_options* opt, float* const* out_rgba, rc_aux* const* aux,
                           void* stream);
 
-/* Reverse mode of rc_render_views (shading NONE): aux[v] and grad_rgba[v] are
+/* Reverse mode of rc_render_views (any shading model): aux[v] and grad_rgba[v] are
  * view v's forward aux and dL/d(rgba); all views accumulate (+=) into one
  * grad_volume_dev and one grad_tf_dev.  Errors: as rc_render_backward. */
 rc_status rc_render_backward_views(const rc_volume* vol, const rc_camera* cams, int n_views,
@@ -272,6 +284,42 @@ rc_status rc_render_backward_views(const rc_volume* vol, const rc_camera* cams, 
                                    const rc_options* opt, const rc_aux* const* aux,
                                    const float* const* grad_rgba, float* grad_volume_dev,
                                    float* grad_tf_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * First-hit surface mode.  The raycaster of Section 3 draws only the
+ * surfaces of the objects in the volume, selected by two thresholds on the
+ * data value (Section 3.11), without transparency (Section 3.9).  A coarse
+ * march finds the first lattice sample inside the window; hitpoint
+ * refinement (Section 5.1, also Section 3.11) then halves the step
+ * `refine_steps` times, moving back from a sample inside the window and
+ * forward from one outside it, which bisects the last coarse interval
+ * (2^n times finer).  A ray whose first sample is already inside (a clip
+ * plane through an object) is not refined.  The refined point is coloured
+ * with the table's rgb at its value, lit with the gradient and shading
+ * model there, and written opaque: (c, 1).  Rays without a surface give
+ * (0,0,0,0).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double step;              /* coarse sample distance in world units, > 0 */
+    double clip_lo[3];        /* clip box in world units, intersected with the volume box */
+    double clip_hi[3];
+    float iso_lo, iso_hi;     /* raw-value window [iso_lo, iso_hi]; iso_lo <= iso_hi, not NaN */
+    int32_t refine_steps;     /* halvings, 0..30 (the paper uses 5 to 6) */
+    int32_t gradient_op;      /* rc_gradient_op, for the shading at the hit */
+    int32_t skip_empty;       /* 1: skip bricks whose value range misses the window
+                                 (needs rc_build_bricks); the image is unchanged */
+    int32_t reserved;         /* must be 0 */
+} rc_surface_options;
+
+/*   tf_rgba_dev  as rc_render (only rgb is used)
+ *   out_rgba_dev device [height][width][4] float32
+ *   t_hit_dev    NULL or device [height][width] float32: ray parameter (world
+ *                units from the ray origin) of the refined hit, +inf without one
+ * Errors: RC_E_INVALID, RC_E_STATE (skip_empty before rc_build_bricks),
+ * RC_E_DEVICE. */
+rc_status rc_render_surface(const rc_volume* vol, const rc_camera* cam, const float* tf_rgba_dev,
+                            int tf_len, const rc_shading* sh, const rc_surface_options* opt,
+                            float* out_rgba_dev, float* t_hit_dev, void* stream);
 
 /* Release a handle and its device memory (synchronises with the device).
  * NULL is ignored. */

@@ -20,6 +20,7 @@ __all__ = [
     "camera_struct", "shading_struct", "options_struct", "library_path",
     "Batch", "rc_batch_create", "rc_batch_render", "rc_batch_destroy", "rc_render_batch",
     "rc_batch_autotune", "rc_render_views", "rc_render_backward_views", "RenderViewsFn",
+    "rc_render_surface", "surface_options_struct",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +55,14 @@ class rc_shading(C.Structure):
 class rc_options(C.Structure):
     _fields_ = [("step", C.c_double), ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3),
                 ("ert_threshold", C.c_float), ("gradient_op", C.c_int32),
-                ("skip_empty", C.c_int32), ("reserved", C.c_int32)]
+                ("skip_empty", C.c_int32), ("reserved", C.c_int32), ("sampling", C.c_int32),
+                ("opacity_ref_step", C.c_float)]
+
+
+class rc_surface_options(C.Structure):
+    _fields_ = [("step", C.c_double), ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3),
+                ("iso_lo", C.c_float), ("iso_hi", C.c_float), ("refine_steps", C.c_int32),
+                ("gradient_op", C.c_int32), ("skip_empty", C.c_int32), ("reserved", C.c_int32)]
 
 
 class rc_stats(C.Structure):
@@ -136,6 +144,10 @@ def _L():
         L.rc_render_backward_views.argtypes = [vp, C.POINTER(rc_camera), C.c_int, vp, C.c_int,
                                                C.POINTER(rc_shading), C.POINTER(rc_options), pp,
                                                pp, vp, vp, vp]
+        L.rc_render_surface.restype = C.c_int
+        L.rc_render_surface.argtypes = [vp, C.POINTER(rc_camera), vp, C.c_int,
+                                        C.POINTER(rc_shading), C.POINTER(rc_surface_options), vp,
+                                        vp, vp]
         _lib = L
     return _lib
 
@@ -178,7 +190,15 @@ def shading_struct(sh: dict) -> rc_shading:
 def options_struct(opt: dict) -> rc_options:
     return rc_options(float(opt["step"]), (C.c_double * 3)(*opt["clip_lo"]),
                       (C.c_double * 3)(*opt["clip_hi"]), float(opt["ert_threshold"]),
-                      GRADIENT_OPS[opt["gradient_op"]], int(bool(opt["skip_empty"])), 0)
+                      GRADIENT_OPS[opt["gradient_op"]], int(bool(opt["skip_empty"])), 0,
+                      int(bool(opt.get("nearest", False))), float(opt.get("ref_step", 0.0)))
+
+
+def surface_options_struct(opt: dict) -> rc_surface_options:
+    return rc_surface_options(float(opt["step"]), (C.c_double * 3)(*opt["clip_lo"]),
+                              (C.c_double * 3)(*opt["clip_hi"]), float(opt["iso_lo"]),
+                              float(opt["iso_hi"]), int(opt["refine"]),
+                              GRADIENT_OPS[opt["gradient_op"]], int(bool(opt["skip_empty"])), 0)
 
 
 # ---------------------------------------------------------------- volumes
@@ -477,3 +497,25 @@ class RenderViewsFn(torch.autograd.Function):
         gv, gtf = rc_render_backward_views(ctx.handle, ctx.cameras, tf, ctx.shading, ctx.options,
                                            list(aux.unbind(0)), list(g.unbind(0)))
         return gv, gtf, None, None, None, None
+
+
+# ---------------------------------------------------------------- first-hit surface mode
+def rc_render_surface(vol: Volume, camera: dict, tf: torch.Tensor, shading: dict, options: dict,
+                      out: torch.Tensor = None, t_hit: torch.Tensor = None, stream=None):
+    """First-hit surface render; returns ``(out [H,W,4], t_hit [H,W] or None)``.
+
+    ``options``: step, gradient_op, iso_lo, iso_hi, refine, skip_empty,
+    clip_lo, clip_hi (rc_surface_options)."""
+    _check_tf(tf)
+    H, W = int(camera["height"]), int(camera["width"])
+    if out is None:
+        out = torch.empty((H, W, 4), dtype=torch.float32, device=tf.device)
+    if out.shape != (H, W, 4) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [H,W,4] tensor")
+    if t_hit is not None and (t_hit.shape != (H, W) or t_hit.dtype != torch.float32
+                              or not t_hit.is_contiguous()):
+        raise ValueError("t_hit must be a contiguous float32 [H,W] tensor")
+    cam, sh, opt = camera_struct(camera), shading_struct(shading), surface_options_struct(options)
+    _check(_L().rc_render_surface(vol.handle, C.byref(cam), _ptr(tf), tf.shape[0], C.byref(sh),
+                                  C.byref(opt), _ptr(out), _ptr(t_hit), _stream(stream)))
+    return out, t_hit

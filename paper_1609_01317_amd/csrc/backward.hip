@@ -1,6 +1,7 @@
-// Reverse mode of the unshaded render: one ray per thread marches back to
-// front from its last composited sample and accumulates dL/dvolume and
-// dL/dtable.  No per-sample state is stored by the forward pass; the
+// Reverse mode of the render: one ray per thread marches back to front
+// from its last composited sample and accumulates dL/dvolume and
+// dL/dtable, through the lighting and the gradient operator's taps when a
+// shading model is on.  No per-sample state is stored by the forward pass; the
 // transmittance in front of each sample is recovered from the final
 // transmittance written to rc_aux.
 #include <cmath>
@@ -25,26 +26,33 @@ __device__ __forceinline__ void add_dtf(const BackwardParams& B, float* lds, int
     else unsafeAtomicAdd(&B.dtf[i * 4 + ch], v);
 }
 
-// Value, table entry pair and colour of lattice sample k (shading NONE).
+// Value, table entry pair, opacity and colour of lattice sample k.  With a
+// shading model the colour is the lit one, also where the opacity is 0:
+// the forward skips the lighting there only because the colour is
+// multiplied by 0, and dC/da needs it.
 struct BwdSample {
     Cell C;
+    int ox[4], oy[4], oz[4];    // footprint offsets in the bricked volume
+    double pv[3];
     float vn;                   // normalised value before clamping
     int i, i1;
     float t;                    // position between entries i and i1
     float4 e0, e1;              // table entries
-    float a;
-    float c[3];
+    float4 rgba;                // table rgb and opacity before correction
+    float a;                    // opacity after correction
+    float da_dtf;               // d a / d (table opacity)
+    float g[3];                 // gradient (shaded renders)
+    float c[3];                 // colour
 };
 
-template <typename VT>
-__device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R, long long k,
+template <typename VT, int OP, bool LIT>
+__device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R,
+                                           const RayShade& rs, long long k, bool lit,
                                            BwdSample& S) {
-    double pv[3];
-    lattice_point(P, R, k, S.C, pv);
+    lattice_point(P, R, k, S.C, S.pv);
     const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
-    int ox[4], oy[4], oz[4];
-    src.offsets(S.C, ox, oy, oz);
-    float v = sample_value<VT>(src.base, ox, oy, oz, S.C);
+    src.offsets(S.C, S.ox, S.oy, S.oz);
+    float v = sample_value<VT>(src.base, S.ox, S.oy, S.oz, S.C);
     S.vn = (v - P.vmin) * P.inv_range;
     float uu = fminf(fmaxf(S.vn, 0.0f), 1.0f) * P.Mm1;
     S.i = min((int)uu, P.M - 1);
@@ -52,10 +60,122 @@ __device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R, 
     S.t = uu - (float)S.i;
     S.e0 = P.tf[S.i];
     S.e1 = P.tf[S.i1];
-    S.a = lerpf(S.e0.w, S.e1.w, S.t);
-    S.c[0] = lerpf(S.e0.x, S.e1.x, S.t);
-    S.c[1] = lerpf(S.e0.y, S.e1.y, S.t);
-    S.c[2] = lerpf(S.e0.z, S.e1.z, S.t);
+    S.rgba = make_float4(lerpf(S.e0.x, S.e1.x, S.t), lerpf(S.e0.y, S.e1.y, S.t),
+                         lerpf(S.e0.z, S.e1.z, S.t), lerpf(S.e0.w, S.e1.w, S.t));
+    S.a = S.rgba.w;
+    S.da_dtf = 1.0f;
+    if (P.ocorr > 0.0f) {
+        // a = 1 - (1 - a_tf)^e: da/da_tf = e (1 - a_tf)^(e - 1) (e at a_tf = 0),
+        // taken as 0 at a_tf = 1 when e < 1
+        float om = 1.0f - S.a;
+        S.da_dtf = (om > 0.0f || P.ocorr >= 1.0f)
+                       ? P.ocorr * __builtin_amdgcn_exp2f((P.ocorr - 1.0f) * __builtin_amdgcn_logf(om))
+                       : 0.0f;
+        if (S.a != 0.0f) S.a = correct_opacity(P, S.a);
+    }
+    S.c[0] = S.rgba.x; S.c[1] = S.rgba.y; S.c[2] = S.rgba.z;
+    if (LIT && lit) {
+        gradient<VT, OP>(P, src.base, S.ox, S.oy, S.oz, S.C, S.g);
+        shade(P, S.rgba, S.g, S.pv, rs, S.c);
+    }
+}
+
+// Reverse of shade(): dL/dc -> dL/d(table rgb) and dL/dG, through the same
+// branches the forward took (max(0, .), the |G| floor).
+__device__ __forceinline__ void shade_adjoint(const RenderParams& P, const BwdSample& S,
+                                              const RayShade& rs, const float dc[3],
+                                              float drgb[3], float dg[3]) {
+    const float* g = S.g;
+    float g2 = fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
+    float rq = __builtin_amdgcn_rsqf(g2), cap = 1.0f / P.grad_eps;
+    bool floored = !(rq < cap);
+    float inv = floored ? cap : rq;
+    float gh[3] = {g[0] * inv, g[1] * inv, g[2] * inv};
+    float L[3], H[3];
+    if (P.light_is_point) {
+        float q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q[a] = P.light[a] - (float)S.pv[a] * P.s[a];
+        float qi = rsq_or_zero(fmaf(q[2], q[2], fmaf(q[1], q[1], q[0] * q[0])));
+        L[0] = q[0] * qi; L[1] = q[1] * qi; L[2] = q[2] * qi;
+        float h[3] = {L[0] + rs.v[0], L[1] + rs.v[1], L[2] + rs.v[2]};
+        float hi = rsq_or_zero(fmaf(h[2], h[2], fmaf(h[1], h[1], h[0] * h[0])));
+        H[0] = h[0] * hi; H[1] = h[1] * hi; H[2] = h[2] * hi;
+    } else {
+        L[0] = P.light[0]; L[1] = P.light[1]; L[2] = P.light[2];
+        H[0] = rs.h[0]; H[1] = rs.h[1]; H[2] = rs.h[2];
+    }
+    const float dc_rgb = fmaf(dc[2], S.rgba.z, fmaf(dc[1], S.rgba.y, dc[0] * S.rgba.x));
+    float dgh[3];
+    if (P.shade == RC_SHADE_PAPER_LAMBERT) {
+        float illum = fmaf(L[2], gh[2], fmaf(L[1], gh[1], L[0] * gh[0]));
+        drgb[0] = dc[0] * illum; drgb[1] = dc[1] * illum; drgb[2] = dc[2] * illum;
+        dgh[0] = dc_rgb * L[0]; dgh[1] = dc_rgb * L[1]; dgh[2] = dc_rgb * L[2];
+    } else {
+        float nl = -fmaf(gh[2], L[2], fmaf(gh[1], L[1], gh[0] * L[0]));
+        float nh = -fmaf(gh[2], H[2], fmaf(gh[1], H[1], gh[0] * H[0]));
+        float k = fmaf(P.kd, fmaxf(nl, 0.0f), P.ka);
+        drgb[0] = dc[0] * k; drgb[1] = dc[1] * k; drgb[2] = dc[2] * k;
+        float wl = nl > 0.0f ? P.kd * dc_rgb : 0.0f;
+        // d/dnh of nh^s = s nh^(s-1) = s spec / nh
+        float wh = 0.0f;
+        if (nh > 0.0f && P.shininess != 0.0f) {
+            float spec = __builtin_amdgcn_exp2f(P.shininess * __builtin_amdgcn_logf(nh));
+            wh = P.ks * (dc[0] + dc[1] + dc[2]) * P.shininess * spec / nh;
+        }
+        // N = -gh
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dgh[a] = -fmaf(wl, L[a], wh * H[a]);
+    }
+    if (floored) {
+        dg[0] = dgh[0] * inv; dg[1] = dgh[1] * inv; dg[2] = dgh[2] * inv;
+    } else {
+        float proj = fmaf(gh[2], dgh[2], fmaf(gh[1], dgh[1], gh[0] * dgh[0]));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dg[a] = (dgh[a] - gh[a] * proj) * inv;
+    }
+}
+
+// Reverse of gradient<VT, OP>: the separable 4x4x4 filters transposed.  A
+// footprint voxel (x, y, z) carries, for dL/dG = (gx, gy, gz) in scaled units,
+//   gx (D'x A'y A'z + gamma D'x Ly Lz) + gy (A'x D'y A'z + gamma Lx D'y Lz)
+//   + gz (A'x A'y D'z + gamma Lx Ly D'z),
+// added to the clamped voxel of the linear gradient array.
+template <int OP>
+__device__ __forceinline__ void gradient_adjoint(const RenderParams& P, const BackwardParams& Bp,
+                                                 const Cell& C, const float dg[3]) {
+    constexpr bool SEP = OpTaps<OP>::kSep;
+    const float gm = OpTaps<OP>::gamma;
+    const float gx = dg[0] * P.gscale[0], gy = dg[1] * P.gscale[1], gz = dg[2] * P.gscale[2];
+    if (gx == 0.0f && gy == 0.0f && gz == 0.0f) return;
+    AxisTaps kx, ky, kz;
+    axis_taps<OP>(C.fr[0], kx);
+    axis_taps<OP>(C.fr[1], ky);
+    axis_taps<OP>(C.fr[2], kz);
+    int xi[4], yi[4], zi[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        xi[i] = clampi(C.c[0] - 1 + i, 0, P.nx - 1);
+        yi[i] = clampi(C.c[1] - 1 + i, 0, P.ny - 1);
+        zi[i] = clampi(C.c[2] - 1 + i, 0, P.nz - 1);
+    }
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            // per-(y, z) factors of the three components
+            const float fxA = SEP ? ky.A[y] * kz.A[z] : 0.0f, fxL = gm * ky.L[y] * kz.L[z];
+            const float fyA = SEP ? ky.D[y] * kz.A[z] : 0.0f, fyL = gm * ky.D[y] * kz.L[z];
+            const float fzA = SEP ? ky.A[y] * kz.D[z] : 0.0f, fzL = gm * ky.L[y] * kz.D[z];
+            const long long row = ((long long)zi[z] * P.ny + yi[y]) * P.nx;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                float w = gx * kx.D[x] * (fxA + fxL);
+                w = fmaf(gy, fmaf(kx.A[x], fyA, kx.L[x] * fyL), w);
+                w = fmaf(gz, fmaf(kx.A[x], fzA, kx.L[x] * fzL), w);
+                if (w != 0.0f) unsafeAtomicAdd(&Bp.dvol[row + xi[x]], w);
+            }
+        }
 }
 
 // Chain rule for one sample (see the forward: C = sum T_k a_k c_k,
@@ -63,26 +183,32 @@ __device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R, 
 //   dL/dc_k = g_rgb T_k a_k
 //   dL/da_k = T_k [ g_rgb . (c_k - Bk1) + g_A Pk1 ]
 // with Bk1 the colour composited behind k (eq. 6 run back to front) and
-// Pk1 the transmittance of the samples behind k.  Then through the table
-// interpolation to u, the clamp to the value, and the trilinear weights.
-template <typename VT>
+// Pk1 the transmittance of the samples behind k.  Then through the
+// lighting to the table rgb and the gradient, through the opacity
+// correction, the table interpolation to u, the clamp to the value, and the
+// trilinear weights; the gradient goes back through the operator's taps.
+template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const BackwardParams& Bp,
-                                               float* lds, const BwdSample& S, float Tk,
-                                               const float4& g, const float Bk1[3], float Pk1) {
+                                               float* lds, const BwdSample& S, const RayShade& rs,
+                                               float Tk, const float4& g, const float Bk1[3],
+                                               float Pk1) {
     float ta = Tk * S.a;
     float dc[3] = {g.x * ta, g.y * ta, g.z * ta};
     float da = Tk * (g.x * (S.c[0] - Bk1[0]) + g.y * (S.c[1] - Bk1[1]) +
-                     g.z * (S.c[2] - Bk1[2]) + g.w * Pk1);
+                     g.z * (S.c[2] - Bk1[2]) + g.w * Pk1) * S.da_dtf;
+    float drgb[3] = {dc[0], dc[1], dc[2]}, dg[3] = {0.f, 0.f, 0.f};
+    if (LIT && S.a != 0.0f) shade_adjoint(P, S, rs, dc, drgb, dg);
     float w0 = 1.0f - S.t, w1 = S.t;
-    const float d4[4] = {dc[0], dc[1], dc[2], da};
+    const float d4[4] = {drgb[0], drgb[1], drgb[2], da};
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
         add_dtf(Bp, lds, S.i, ch, w0 * d4[ch]);
         add_dtf(Bp, lds, S.i1, ch, w1 * d4[ch]);
     }
+    if (LIT) gradient_adjoint<OP>(P, Bp, S.C, dg);
     if (!(S.vn > 0.0f && S.vn < 1.0f)) return;      // clamped: no dependence on the value
-    float du = dc[0] * (S.e1.x - S.e0.x) + dc[1] * (S.e1.y - S.e0.y) +
-               dc[2] * (S.e1.z - S.e0.z) + da * (S.e1.w - S.e0.w);
+    float du = drgb[0] * (S.e1.x - S.e0.x) + drgb[1] * (S.e1.y - S.e0.y) +
+               drgb[2] * (S.e1.z - S.e0.z) + da * (S.e1.w - S.e0.w);
     float dv = du * P.Mm1 * P.inv_range;
     if (dv == 0.0f) return;
     const float fx = S.C.fr[0], fy = S.C.fr[1], fz = S.C.fr[2];
@@ -93,6 +219,7 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
 #pragma unroll
             for (int cx = 0; cx < 2; ++cx) {
                 float w = (cx ? fx : 1.0f - fx) * (cy ? fy : 1.0f - fy) * (cz ? fz : 1.0f - fz);
+                if (w == 0.0f) continue;        // nearest sampling: one corner only
                 int x = clampi(S.C.c[0] + cx, 0, P.nx - 1);
                 int y = clampi(S.C.c[1] + cy, 0, P.ny - 1);
                 int z = clampi(S.C.c[2] + cz, 0, P.nz - 1);
@@ -101,8 +228,9 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
 }
 
 // One workgroup = one 16x16 pixel tile of one view; views own consecutive
-// runs of workgroups (ViewSet::block_off).
-template <typename VT>
+// runs of workgroups (ViewSet::block_off).  LIT: a shading model is on (the
+// unshaded kernel carries none of the lighting and stencil registers).
+template <typename VT, int OP, bool LIT>
 __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
     extern __shared__ float lds[];
     if (Bp.lds_tf) {
@@ -120,6 +248,8 @@ __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, Ba
     if (px < V.W && py < V.H) {
         Ray R;
         setup_ray(P, V, px, py, R);
+        RayShade rs;
+        ray_shade(P, R, rs);
         long long pix = (long long)py * V.W + px;
         rc_aux ax = V.aux[pix];
         float4 g = V.grad[pix];
@@ -135,7 +265,7 @@ __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, Ba
                 anchor = 0;
                 for (long long k = 0; k <= last; ++k) {
                     BwdSample S;
-                    bwd_sample<VT>(P, R, k, S);
+                    bwd_sample<VT, OP, LIT>(P, R, rs, k, false, S);
                     float Tn = T * (1.0f - S.a);
                     if (!(Tn >= kTinyT)) break;
                     T = Tn;
@@ -148,12 +278,12 @@ __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, Ba
             float Q = 1.0f;         // prod over samples k .. anchor-1 of (1 - a)
             for (long long k = last; k >= 0; --k) {
                 BwdSample S;
-                bwd_sample<VT>(P, R, k, S);
+                bwd_sample<VT, OP, LIT>(P, R, rs, k, true, S);
                 float om = 1.0f - S.a;
                 if (k < anchor) {
                     Q *= om;
                     float Tk = Q > 0.0f ? Ta / Q : 0.0f;
-                    bwd_accumulate<VT>(P, Bp, lds, S, Tk, g, Bk1, Pk1);
+                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, S, rs, Tk, g, Bk1, Pk1);
                 }
                 Bk1[0] = fmaf(S.a, S.c[0], om * Bk1[0]);
                 Bk1[1] = fmaf(S.a, S.c[1], om * Bk1[1]);
@@ -171,6 +301,21 @@ __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, Ba
     }
 }
 
+template <typename VT>
+static void launch_bwd_t(const RenderParams& P, const ViewSet& S, const BackwardParams& Bp, int op,
+                         dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    if (P.shade == RC_SHADE_NONE)
+        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s, P, S,
+                           Bp);
+    else if (op == RC_GRAD_CENTRAL)
+        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_CENTRAL, true>), grid, block, lds, s, P, S, Bp);
+    else if (op == RC_GRAD_SOBEL3D)
+        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_SOBEL3D, true>), grid, block, lds, s, P, S, Bp);
+    else
+        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_ZUCKER_HUMMEL, true>), grid, block, lds, s, P,
+                           S, Bp);
+}
+
 }  // namespace rc
 
 using namespace rc;
@@ -184,8 +329,6 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
         rc_status st = check_render_args(v, &cams[i], tf_rgba_dev, tf_len, sh, opt);
         if (st != RC_OK) return n_views > 1 ? fail(st, "view %d: %s", i, rc_last_error()) : st;
     }
-    if (sh->model != RC_SHADE_NONE)
-        return fail(RC_E_UNSUPPORTED, "rc_render_backward: only shading NONE is differentiated");
     for (int i = 0; i < n_views; ++i)
         if (!aux[i] || !grad_rgba[i])
             return fail(RC_E_INVALID, "rc_render_backward: aux/grad pointers must not be NULL");
@@ -212,12 +355,10 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
         }
         S.block_off[S.n] = off;
         dim3 grid((unsigned)off), block(kBwdTile * kBwdTile);
-        if (v->dtype == RC_U8)
-            hipLaunchKernelGGL(raycast_bwd<uint8_t>, grid, block, lds, s, P, S, Bp);
-        else if (v->dtype == RC_U16)
-            hipLaunchKernelGGL(raycast_bwd<uint16_t>, grid, block, lds, s, P, S, Bp);
-        else
-            hipLaunchKernelGGL(raycast_bwd<float>, grid, block, lds, s, P, S, Bp);
+        int op = opt->gradient_op;
+        if (v->dtype == RC_U8) launch_bwd_t<uint8_t>(P, S, Bp, op, grid, block, lds, s);
+        else if (v->dtype == RC_U16) launch_bwd_t<uint16_t>(P, S, Bp, op, grid, block, lds, s);
+        else launch_bwd_t<float>(P, S, Bp, op, grid, block, lds, s);
         RC_HIP(hipGetLastError());
     }
     return RC_OK;

@@ -1,7 +1,8 @@
 // Batched rendering: many images of many volumes in one persistent launch.
 // Each item is the argument set of one rc_render call.  Resident waves pull
 // (item, tile) work units from a device counter until the queue is empty;
-// the per-item empty-brick masks are built by two batched kernels; the
+// the per-item empty-brick and super-brick masks are built by three batched
+// kernels; the
 // whole sequence can be captured into a HIP graph and replayed.
 #include <algorithm>
 #include <cmath>
@@ -23,6 +24,9 @@ struct MaskJob {
     long long nbricks;
     long long brick_off;        // offset into the concatenated mask array
     long long prefix_off;       // offset into the concatenated prefix array
+    int nbx, nby, nbz, nsx, nsy;
+    long long nsuper;
+    long long super_off;        // offset into the concatenated super mask array
 };
 
 // ---------------------------------------------------------------- kernels
@@ -81,6 +85,34 @@ __global__ __launch_bounds__(256) void batch_mask(const MaskJob* __restrict__ jo
     mask_all[g] = (prefix[ihi + 1] - prefix[ilo]) == 0;
 }
 
+// one thread per super-brick of every mask job (same rule as the single-render
+// super mask: empty iff all of its bricks are)
+__global__ __launch_bounds__(256) void batch_super(const MaskJob* __restrict__ jobs, int njobs,
+                                                   long long total,
+                                                   const uint8_t* __restrict__ mask_all,
+                                                   uint8_t* __restrict__ super_all) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    int lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (jobs[mid].super_off <= g) lo = mid; else hi = mid;
+    }
+    const MaskJob& J = jobs[lo];
+    long long sidx = g - J.super_off;
+    if (sidx < 0 || sidx >= J.nsuper) return;
+    const uint8_t* mask = mask_all + J.brick_off;
+    int sx = (int)(sidx % J.nsx);
+    long long rest = sidx / J.nsx;
+    int sy = (int)(rest % J.nsy), sz = (int)(rest / J.nsy);
+    uint8_t all = 1;
+    for (int bz = sz * 4; bz < min(sz * 4 + 4, J.nbz); ++bz)
+        for (int by = sy * 4; by < min(sy * 4 + 4, J.nby); ++by)
+            for (int bx = sx * 4; bx < min(sx * 4 + 4, J.nbx); ++bx)
+                all &= mask[((long long)bz * J.nby + by) * J.nbx + bx];
+    super_all[g] = all;
+}
+
 // The persistent kernel.  `kind` = dtype * 3 + gradient operator selects the
 // instantiation per work unit (uniform across the wave).
 __global__ __launch_bounds__(256) void raycast_batch(const RenderParams* __restrict__ items,
@@ -129,6 +161,7 @@ struct rc_batch {
     int total_tiles;
     int n_jobs;
     long long total_bricks;
+    long long total_super;
     int grid;
     void* dmem;                 // one allocation holding everything below
     RenderParams* d_items;
@@ -139,6 +172,7 @@ struct rc_batch {
     MaskJob* d_jobs;
     int* d_prefix;
     uint8_t* d_mask;
+    uint8_t* d_super;
     hipGraph_t graph;
     hipGraphExec_t exec;
     bool captured;
@@ -170,7 +204,7 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     std::vector<RenderParams> P(n);
     std::vector<int> kinds(n), tiles(n);
     std::vector<MaskJob> jobs;
-    long long total_bricks = 0, total_prefix = 0;
+    long long total_bricks = 0, total_prefix = 0, total_super = 0;
     for (int i = 0; i < n; ++i) {
         const rc_batch_item& it = items[i];
         st = check_render_args(it.vol, &it.cam, it.tf_rgba_dev, it.tf_len, &it.sh, &it.opt);
@@ -194,8 +228,16 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
             J.nbricks = it.vol->nbricks;
             J.brick_off = total_bricks;
             J.prefix_off = total_prefix;
+            J.nbx = it.vol->nbx;
+            J.nby = it.vol->nby;
+            J.nbz = it.vol->nbz;
+            J.nsx = it.vol->nsx;
+            J.nsy = it.vol->nsy;
+            J.nsuper = it.vol->nsuper;
+            J.super_off = total_super;
             total_bricks += J.nbricks;
             total_prefix += it.tf_len + 1;
+            total_super += J.nsuper;
             jobs.push_back(J);
         }
     }
@@ -221,7 +263,8 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     size_t o_jobs = align256(o_counter + sizeof(int));
     size_t o_prefix = align256(o_jobs + sizeof(MaskJob) * std::max<size_t>(jobs.size(), 1));
     size_t o_mask = align256(o_prefix + sizeof(int) * std::max<long long>(total_prefix, 1));
-    size_t bytes = align256(o_mask + std::max<long long>(total_bricks, 1));
+    size_t o_super = align256(o_mask + std::max<long long>(total_bricks, 1));
+    size_t bytes = align256(o_super + std::max<long long>(total_super, 1));
 
     rc_batch* b = new (std::nothrow) rc_batch();
     if (!b) return fail(RC_E_OOM, "rc_batch_create: host allocation failed");
@@ -230,6 +273,7 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     b->total_tiles = (int)total;
     b->n_jobs = (int)jobs.size();
     b->total_bricks = total_bricks;
+    b->total_super = total_super;
     b->captured = false;
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipMalloc(&b->dmem, bytes);
@@ -243,8 +287,13 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     b->d_jobs = (MaskJob*)(base + o_jobs);
     b->d_prefix = (int*)(base + o_prefix);
     b->d_mask = (uint8_t*)(base + o_mask);
+    b->d_super = (uint8_t*)(base + o_super);
     for (int i = 0, j = 0; i < n; ++i)
-        if (items[i].opt.skip_empty) P[i].empty = b->d_mask + jobs[j++].brick_off;
+        if (items[i].opt.skip_empty) {
+            P[i].empty = b->d_mask + jobs[j].brick_off;
+            P[i].super_empty = b->d_super + jobs[j].super_off;
+            ++j;
+        }
     hipStream_t s = (hipStream_t)stream;
     e = hipMemcpyAsync(b->d_items, P.data(), sizeof(RenderParams) * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -279,6 +328,9 @@ static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
         unsigned g = (unsigned)((b->total_bricks + 255) / 256);
         hipLaunchKernelGGL(batch_mask, dim3(g), dim3(256), 0, s, b->d_jobs, b->n_jobs,
                            b->total_bricks, b->d_prefix, b->d_mask);
+        g = (unsigned)((b->total_super + 255) / 256);
+        hipLaunchKernelGGL(batch_super, dim3(g), dim3(256), 0, s, b->d_jobs, b->n_jobs,
+                           b->total_super, b->d_mask, b->d_super);
     }
     hipLaunchKernelGGL(raycast_batch, dim3(b->grid), dim3(64 * b->cfg.waves_per_wg),
                        (size_t)kWaveLdsBytes * b->cfg.waves_per_wg, s,
@@ -348,7 +400,8 @@ static std::string batch_key(const rc_batch_item* items, int n) {
              std::to_string(it.vol->nz) + ":" + std::to_string((int)it.vol->dtype) + ":" +
              std::to_string(it.cam.width) + "x" + std::to_string(it.cam.height) + ":" +
              std::to_string(it.opt.gradient_op) + ":" + std::to_string(it.sh.model) + ":" +
-             std::to_string(it.opt.skip_empty) + ";";
+             std::to_string(it.opt.skip_empty) + ":" + std::to_string(it.opt.sampling) + ":" +
+             std::to_string(it.opt.opacity_ref_step > 0.0f) + ";";
     }
     char buf[32];
     snprintf(buf, sizeof buf, "%016llx", fnv1a(k));

@@ -65,6 +65,30 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// ---------------------------------------------------------------- tile placement
+// Workgroup = one wave = one pixel tile.  Workgroups are dealt to the 8 XCDs
+// round-robin by block index.  Tiles are grouped 4x4 (32x32 pixels) and the
+// groups are dealt round-robin to the XCDs: neighbouring tiles of a group
+// share one XCD's L2, and every XCD gets groups from all over the image, so
+// the dense middle of a volume is not left to one or two XCDs.
+constexpr int kGroupTiles = 4;
+
+__host__ __device__ inline int group_grid_blocks(int tiles_x, int tiles_y) {
+    int gx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
+    int gy = (tiles_y + kGroupTiles - 1) / kGroupTiles;
+    return ((gx * gy + 7) / 8) * 8 * kGroupTiles * kGroupTiles;
+}
+
+__device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
+    const int per = kGroupTiles * kGroupTiles;
+    int gx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
+    int xcd = b & 7, q = b >> 3;
+    int g = (q / per) * 8 + xcd, pos = q % per;
+    int tx = (g % gx) * kGroupTiles + pos % kGroupTiles;
+    int ty = (g / gx) * kGroupTiles + pos / kGroupTiles;
+    return (tx < tiles_x && ty < tiles_y) ? ty * tiles_x + tx : -1;
+}
+
 // ---------------------------------------------------------------- ray set-up
 // Camera ray through the centre of pixel (px, py) and its span inside the
 // sampling box (Section 3.3: no intersection -> black; two -> sample between).
@@ -114,24 +138,32 @@ __device__ inline void setup_ray(const RenderParams& P, const ViewParams& V, int
     if (hit && tmin <= tmax) R.K = (long long)floor((tmax - tmin) / P.step);
 }
 
-// Voxel-space position of lattice sample k: cell index and fraction.
+// Voxel-space position of the point at ray parameter t (lattice_point: of
+// lattice sample k): cell index and fraction.
 struct Cell {
     int c[3];
     float fr[3];
 };
 
-__device__ __forceinline__ void lattice_point(const RenderParams& P, const Ray& R, long long k,
-                                              Cell& C, double pv[3]) {
-    double t = R.t_in + (double)k * P.step;
+__device__ __forceinline__ void point_at(const RenderParams& P, const Ray& R, double t, Cell& C,
+                                         double pv[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double p = (R.o[a] + t * R.d[a]) * P.inv_s[a];
         pv[a] = p;
-        double fl = floor(p);
+        // nearest sampling (Section 3.3, round half up): the cell of the
+        // rounded point with fraction 0, so the trilinear and stencil code
+        // reduce exactly to that voxel
+        double fl = floor(P.nearest ? p + 0.5 : p);
         fl = fmin(fmax(fl, -2.0), 1.0e7);
         C.c[a] = (int)fl;
-        C.fr[a] = (float)(p - fl);
+        C.fr[a] = P.nearest ? 0.0f : (float)(p - fl);
     }
+}
+
+__device__ __forceinline__ void lattice_point(const RenderParams& P, const Ray& R, long long k,
+                                              Cell& C, double pv[3]) {
+    point_at(P, R, R.t_in + (double)k * P.step, C, pv);
 }
 
 // ---------------------------------------------------------------- voxel sources
@@ -457,6 +489,12 @@ struct MarchOut {
     unsigned chunks_staged, chunks_empty, chunks_direct;  // per wave (uniform)
 };
 
+// Opacity correction for the sample distance: a = 1 - (1 - a_tf)^(step/ref),
+// through hardware log2 / exp2 (0 stays 0, 1 stays 1).
+__device__ __forceinline__ float correct_opacity(const RenderParams& P, float a) {
+    return 1.0f - __builtin_amdgcn_exp2f(P.ocorr * __builtin_amdgcn_logf(1.0f - a));
+}
+
 // Per-lane compositing state (Section 3.9, eq. 6 evaluated front to back:
 // C += T a c, T *= 1 - a; early termination after the first sample with
 // 1 - T >= tau).
@@ -488,6 +526,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     float4 rgba = tf_lookup(P, v);
     float a = rgba.w;
     if (a == 0.0f) return false;
+    if (P.ocorr > 0.0f) a = correct_opacity(P, a);
     ++S.shaded;
     float c[3] = {rgba.x, rgba.y, rgba.z};
     if (P.shade != RC_SHADE_NONE) {
@@ -544,8 +583,74 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
     }
 }
 
-// Chunk lengths in lattice steps.
+// Chunk lengths in lattice steps; super-chunks test 32^3 super-bricks.
 constexpr int kChunkMin = 2, kChunkInit = 16, kChunkMax = 128;
+constexpr int kSuperMin = 64, kSuperInit = 256;
+
+// This lane's lattice samples in [tau, tau + len * step): indices S.k ..
+// kstop (kstop < S.k when it has none), and the wave-wide bounds of their
+// cells.  Returns false when no lane of the wave has a sample there.
+__device__ __forceinline__ bool chunk_cells(const RenderParams& P, const Ray& R, bool active,
+                                            long long k, double tau, int len, long long& kstop,
+                                            int cmin[3], int cmax[3]) {
+    double tau_end = tau + (double)len * P.step;
+    kstop = -1;
+    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+    if (active) {
+        double q = ceil((tau_end - R.t_in) / P.step) - 1.0;
+        kstop = q < (double)R.K ? (long long)fmax(q, -1.0) : R.K;
+        // the lane(s) defining tau always own at least their next sample
+        if (R.t_in + (double)k * P.step < tau_end && kstop < k) kstop = k;
+        if (kstop >= k) {
+            // cells are monotone along a straight ray: the end points bound them
+            Cell c0, c1;
+            double pv[3];
+            lattice_point(P, R, k, c0, pv);
+            lattice_point(P, R, kstop, c1, pv);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = min(c0.c[a], c1.c[a]);
+                mx[a] = max(c0.c[a], c1.c[a]);
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cmin[a] = wave_min(mn[a]);
+        cmax[a] = wave_max(mx[a]);
+    }
+    return cmin[0] <= cmax[0];
+}
+
+// Super-brick test of the chunk [tau, tau + len * step), shrinking len until
+// its cells span at most 64 super-bricks.  Returns true when every one of
+// them is empty; kstop is then this lane's last sample in the chunk.
+__device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const Ray& R, bool active,
+                                                  long long k, double tau, int& len,
+                                                  long long& kstop, int lane) {
+    const int n[3] = {P.nx, P.ny, P.nz};
+    for (;; len >>= 1) {
+        int cmin[3], cmax[3];
+        if (!chunk_cells(P, R, active, k, tau, len, kstop, cmin, cmax)) return false;
+        int slo[3], sdim[3], nsr = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            slo[a] = clampi(cmin[a], 0, n[a] - 1) >> 5;
+            sdim[a] = (clampi(cmax[a], 0, n[a] - 1) >> 5) - slo[a] + 1;
+            nsr *= sdim[a];
+        }
+        if (nsr > 64) {
+            if (len <= kSuperMin) return false;
+            continue;
+        }
+        bool live = false;
+        if (lane < nsr) {
+            int r0 = lane % sdim[0], r1 = (lane / sdim[0]) % sdim[1], r2 = lane / (sdim[0] * sdim[1]);
+            live = P.super_empty[((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0] == 0;
+        }
+        return __ballot(live) == 0ull;
+    }
+}
 
 // March the 64 rays of this wave together.  `has_ray` is false for lanes
 // outside the image; they still take part in the wave-wide steps.
@@ -568,6 +673,8 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
     const int cap = kWaveLdsBytes / (int)sizeof(VT);
     int len = kChunkInit;
+    // a super-chunk is tried at the start and after every empty chunk
+    bool try_super = P.skip && P.super_empty != nullptr;
     for (;;) {
         bool active = !S.done && S.k <= R.K;
         if (!active) S.done = true;
@@ -576,36 +683,22 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
         double tau = wave_min(active ? R.t_in + (double)S.k * P.step : INFINITY);
         Chunk ch;
         long long kstop = -1;
+        if (try_super) {
+            // grows with the brick chunk length (up to 1024 after empty chunks)
+            int slen = max(len * 8, kSuperInit);
+            if (super_chunk_empty(P, R, active, S.k, tau, slen, kstop, lane)) {
+                ++n_empty;
+                if (active && kstop >= S.k) S.k = kstop + 1;
+                len = min(len * 2, kChunkMax);
+                continue;
+            }
+            try_super = false;
+        }
         bool fits = false;
         for (;;) {
-            double tau_end = tau + (double)len * P.step;
-            kstop = -1;
-            int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
-            if (active) {
-                double q = ceil((tau_end - R.t_in) / P.step) - 1.0;
-                kstop = q < (double)R.K ? (long long)fmax(q, -1.0) : R.K;
-                // the lane(s) defining tau always own at least their next sample
-                if (R.t_in + (double)S.k * P.step < tau_end && kstop < S.k) kstop = S.k;
-                if (kstop >= S.k) {
-                    Cell c0, c1;
-                    double pv[3];
-                    lattice_point(P, R, S.k, c0, pv);
-                    lattice_point(P, R, kstop, c1, pv);
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        mn[a] = min(c0.c[a], c1.c[a]);
-                        mx[a] = max(c0.c[a], c1.c[a]);
-                    }
-                }
-            }
             int cmin[3], cmax[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cmin[a] = wave_min(mn[a]);
-                cmax[a] = wave_max(mx[a]);
-            }
-            if (cmin[0] > cmax[0]) {            // no lane has a sample before tau_end
-                fits = false;
+            if (!chunk_cells(P, R, active, S.k, tau, len, kstop, cmin, cmax)) {
+                fits = false;                   // no lane has a sample in the chunk
                 ch.mask_valid = false;
                 for (int a = 0; a < 3; ++a) ch.lo[a] = ch.dim[a] = ch.blo[a] = ch.bdim[a] = 0;
                 break;
@@ -643,6 +736,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
                 ++n_empty;
                 if (active && kstop >= S.k) S.k = kstop + 1;
                 len = min(len * 2, kChunkMax);
+                try_super = P.super_empty != nullptr;
                 continue;
             }
         }

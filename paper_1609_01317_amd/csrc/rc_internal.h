@@ -20,6 +20,9 @@ struct rc_volume {
     long long nbricks;
     void* bricked;              // nbricks * 512 voxels of dtype
     float2* brick_range;        // nbricks (min, max) or null before rc_build_bricks
+    // super-bricks: 4x4x4 bricks (32^3 voxels); empty iff all their bricks are
+    int nsx, nsy, nsz;
+    long long nsuper;
     int device;
 };
 
@@ -95,7 +98,11 @@ struct RenderParams {
     // options
     float tau;
     int skip;
+    int nearest;                // 1: nearest-voxel sampling
+    float ocorr;                // opacity-correction exponent step / ref_step, 0 = off
     const uint8_t* empty;       // per-brick flag, 1 = every sample has alpha 0
+    const uint8_t* super_empty; // per-super-brick flag (4x4x4 bricks), or null
+    int nsx, nsy;               // super-bricks per row / per slab row
     rc_stats* stats;            // kStatSlots consecutive copies, or null
 };
 
@@ -117,7 +124,13 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
 // Launch the prefix + empty-mask kernels into `mask` (nbricks bytes) using
 // `prefix` (tf_len + 1 ints) as scratch.
 rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
-                            int* prefix, hipStream_t st);
+                            uint8_t* super_mask, int* prefix, hipStream_t st);
+// super_mask[s] = AND of the brick flags of super-brick s (one thread each).
+__global__ void super_mask_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ smask,
+                                  int nbx, int nby, int nbz, int nsx, int nsy, long long nsuper);
+// Bytes of per-render skip scratch: brick mask, super-brick mask, prefix counts.
+size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
+                          size_t* super_bytes);
 void set_tiling(ViewParams& V, int tile_w);     // tile_w in {4, 8, 16, 32, 64}
 void fill_view(ViewParams& V, const rc_camera* cam);
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);

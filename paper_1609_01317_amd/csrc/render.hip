@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void empty_mask(const float2* __restrict__ ran
 }
 
 rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
-                            int* prefix, hipStream_t st) {
+                            uint8_t* super_mask, int* prefix, hipStream_t st) {
     float inv_range = (float)(1.0 / ((double)v->vmax - (double)v->vmin));
     hipLaunchKernelGGL(tf_alpha_prefix, dim3(1), dim3(256), 0, st, (const float4*)tf, tf_len,
                        prefix);
@@ -62,33 +62,39 @@ rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uin
     hipLaunchKernelGGL(empty_mask, dim3(grid), dim3(256), 0, st, v->brick_range, prefix, tf_len,
                        v->vmin, inv_range, (float)(tf_len - 1), mask, v->nbricks);
     RC_HIP(hipGetLastError());
+    grid = (unsigned)((v->nsuper + 255) / 256);
+    hipLaunchKernelGGL(super_mask_kernel, dim3(grid), dim3(256), 0, st, mask, super_mask, v->nbx,
+                       v->nby, v->nbz, v->nsx, v->nsy, v->nsuper);
+    RC_HIP(hipGetLastError());
     return RC_OK;
 }
 
+__global__ __launch_bounds__(256) void super_mask_kernel(const uint8_t* __restrict__ mask,
+                                                         uint8_t* __restrict__ smask, int nbx,
+                                                         int nby, int nbz, int nsx, int nsy,
+                                                         long long nsuper) {
+    long long sidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sidx >= nsuper) return;
+    int sx = (int)(sidx % nsx);
+    long long rest = sidx / nsx;
+    int sy = (int)(rest % nsy), sz = (int)(rest / nsy);
+    uint8_t all = 1;
+    for (int bz = sz * 4; bz < min(sz * 4 + 4, nbz); ++bz)
+        for (int by = sy * 4; by < min(sy * 4 + 4, nby); ++by)
+            for (int bx = sx * 4; bx < min(sx * 4 + 4, nbx); ++bx)
+                all &= mask[((long long)bz * nby + by) * nbx + bx];
+    smask[sidx] = all;
+}
+
+size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
+                          size_t* super_bytes) {
+    *mask_bytes = ((size_t)v->nbricks + 255) & ~(size_t)255;
+    *super_bytes = ((size_t)v->nsuper + 255) & ~(size_t)255;
+    return *mask_bytes + *super_bytes + sizeof(int) * ((size_t)tf_len + 1);
+}
+
 // ---------------------------------------------------------------- the kernel
-// Workgroup = one wave = one pixel tile.  Workgroups are dealt to the 8 XCDs
-// round-robin by block index.  Tiles are grouped 4x4 (32x32 pixels) and the
-// groups are dealt round-robin to the XCDs: neighbouring tiles of a group
-// share one XCD's L2, and every XCD gets groups from all over the image, so
-// the dense middle of a volume is not left to one or two XCDs.
-constexpr int kGroupTiles = 4;
-
-__host__ __device__ inline int group_grid_blocks(int tiles_x, int tiles_y) {
-    int gx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
-    int gy = (tiles_y + kGroupTiles - 1) / kGroupTiles;
-    return ((gx * gy + 7) / 8) * 8 * kGroupTiles * kGroupTiles;
-}
-
-__device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
-    const int per = kGroupTiles * kGroupTiles;
-    int gx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
-    int xcd = b & 7, q = b >> 3;
-    int g = (q / per) * 8 + xcd, pos = q % per;
-    int tx = (g % gx) * kGroupTiles + pos % kGroupTiles;
-    int ty = (g / gx) * kGroupTiles + pos / kGroupTiles;
-    return (tx < tiles_x && ty < tiles_y) ? ty * tiles_x + tx : -1;
-}
-
+// Workgroup = one wave = one pixel tile, placed by tile_of_block.
 template <typename VT, int OP>
 __global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
     __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
@@ -249,6 +255,10 @@ rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const floa
     if (opt->skip_empty != 0 && opt->skip_empty != 1)
         return fail(RC_E_INVALID, "options: skip_empty must be 0 or 1");
     if (opt->reserved != 0) return fail(RC_E_INVALID, "options: reserved field must be 0");
+    if (opt->sampling != RC_SAMPLE_TRILINEAR && opt->sampling != RC_SAMPLE_NEAREST)
+        return fail(RC_E_INVALID, "options: unknown sampling %d", opt->sampling);
+    if (!(std::isfinite(opt->opacity_ref_step) && opt->opacity_ref_step >= 0.0f))
+        return fail(RC_E_INVALID, "options: opacity_ref_step must be finite and >= 0");
     for (int a = 0; a < 3; ++a)
         if (std::isnan(opt->clip_lo[a]) || std::isnan(opt->clip_hi[a]))
             return fail(RC_E_INVALID, "options: clip box has NaN");
@@ -345,7 +355,14 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     P.grad_eps = sh->grad_eps;
     P.tau = opt->ert_threshold;
     P.skip = opt->skip_empty;
+    P.nearest = opt->sampling == RC_SAMPLE_NEAREST;
+    // exponent 1 is the identity: left off (0) so no kernel meets 0^0
+    double e = opt->opacity_ref_step > 0.0f ? opt->step / (double)opt->opacity_ref_step : 0.0;
+    P.ocorr = e == 1.0 ? 0.0f : (float)e;
     P.empty = nullptr;
+    P.super_empty = nullptr;
+    P.nsx = v->nsx;
+    P.nsy = v->nsy;
     P.stats = nullptr;
 }
 
@@ -367,11 +384,11 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
     P.view.aux = aux_dev;
     // per-render scratch: counter slots, empty mask, table prefix counts
     const size_t stat_bytes = stats_dev ? sizeof(rc_stats) * kStatSlots : 0;
-    const size_t mask_bytes = opt->skip_empty ? (((size_t)v->nbricks + 255) & ~(size_t)255) : 0;
-    const size_t prefix_bytes = opt->skip_empty ? sizeof(int) * ((size_t)tf_len + 1) : 0;
+    size_t mask_bytes = 0, super_bytes = 0;
+    const size_t skip_bytes =
+        opt->skip_empty ? skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes) : 0;
     void* scratch = nullptr;
-    if (stat_bytes + mask_bytes + prefix_bytes > 0)
-        RC_HIP(hipMallocAsync(&scratch, stat_bytes + mask_bytes + prefix_bytes, s));
+    if (stat_bytes + skip_bytes > 0) RC_HIP(hipMallocAsync(&scratch, stat_bytes + skip_bytes, s));
     char* sp = (char*)scratch;
     if (stats_dev) {
         P.stats = (rc_stats*)sp;
@@ -381,9 +398,11 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
     }
     if (st == RC_OK && opt->skip_empty) {
         uint8_t* mask = (uint8_t*)(sp + stat_bytes);
-        int* prefix = (int*)(sp + stat_bytes + mask_bytes);
-        st = launch_empty_mask(v, tf_rgba_dev, tf_len, mask, prefix, s);
+        uint8_t* smask = mask + mask_bytes;
+        int* prefix = (int*)(smask + super_bytes);
+        st = launch_empty_mask(v, tf_rgba_dev, tf_len, mask, smask, prefix, s);
         P.empty = mask;
+        P.super_empty = smask;
     }
     if (st == RC_OK) st = launch_forward(P, v->dtype, opt->gradient_op, s);
     if (st == RC_OK && stats_dev) {
@@ -418,11 +437,14 @@ extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, 
     rc_status st = RC_OK;
     void* scratch = nullptr;
     if (opt->skip_empty) {
-        const size_t mask_bytes = ((size_t)v->nbricks + 255) & ~(size_t)255;
-        RC_HIP(hipMallocAsync(&scratch, mask_bytes + sizeof(int) * ((size_t)tf_len + 1), s));
+        size_t mask_bytes, super_bytes;
+        RC_HIP(hipMallocAsync(&scratch, skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes),
+                              s));
         P.empty = (uint8_t*)scratch;
-        st = launch_empty_mask(v, tf_rgba_dev, tf_len, (uint8_t*)scratch,
-                               (int*)((char*)scratch + mask_bytes), s);
+        P.super_empty = P.empty + mask_bytes;
+        st = launch_empty_mask(v, tf_rgba_dev, tf_len, (uint8_t*)P.empty,
+                               (uint8_t*)P.super_empty,
+                               (int*)((char*)scratch + mask_bytes + super_bytes), s);
     }
     for (int first = 0; st == RC_OK && first < n_views; first += kMaxViews) {
         ViewSet S;

@@ -166,6 +166,8 @@ extern "C" rc_status rc_create_volume(const void* src_dev, int nx, int ny, int n
     v->nbx = nbx; v->nby = nby; v->nbz = nbz;
     v->nbricks = nbricks;
     v->brick_range = nullptr;
+    v->nsx = (nbx + 3) / 4; v->nsy = (nby + 3) / 4; v->nsz = (nbz + 3) / 4;
+    v->nsuper = (long long)v->nsx * v->nsy * v->nsz;
     hipError_t e = hipGetDevice(&v->device);
     if (e != hipSuccess) { delete v; return hip_fail(e, "hipGetDevice"); }
     e = hipMalloc(&v->bricked, (size_t)nbricks * kBrickVox * v->elem_bytes);

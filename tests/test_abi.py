@@ -39,10 +39,11 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert C.sizeof(rc.rc_camera) == 16 + 11 * 8
     assert C.sizeof(rc.rc_shading) == 8 + 4 * 4 + 3 * 4 + 4
-    assert C.sizeof(rc.rc_options) == 8 + 6 * 8 + 4 * 4
+    assert C.sizeof(rc.rc_options) == 8 + 6 * 8 + 6 * 4
     assert C.sizeof(rc.rc_stats) == 64
-    assert C.sizeof(rc.rc_batch_item) == 256
+    assert C.sizeof(rc.rc_batch_item) == 264
     assert C.sizeof(rc.rc_batch_config) == 16
+    assert C.sizeof(rc.rc_surface_options) == 8 + 6 * 8 + 2 * 4 + 4 * 4
 
 
 def _status(fn, *args):
@@ -100,3 +101,24 @@ def test_batch_rejects_bad_arguments_on_host():
     st, _ = _status("rc_batch_autotune", items, 1, None, None, C.byref(rc.rc_batch_config()))
     assert st == rc.RC_E_INVALID
     rc._L().rc_batch_destroy(None)
+
+
+def test_surface_rejects_bad_arguments_on_host():
+    import workloads as W
+    cam = rc.camera_struct(W.orbit_camera((8, 8, 8), (1, 1, 1), 0, 0, 8, 8))
+    sh = rc.shading_struct(W.default_shading())
+    tf, out = C.c_void_p(0x1000), C.c_void_p(0x2000)
+    st, msg = _status("rc_render_surface", None, C.byref(cam), tf, 256, C.byref(sh), None, out,
+                      None, None)
+    assert st == rc.RC_E_INVALID and "options" in msg
+    good = W.default_surface_options(iso_lo=10.0, iso_hi=20.0)
+    for bad, word in [(dict(good, iso_lo=float("nan")), "iso"), (dict(good, iso_lo=30.0), "iso"),
+                      (dict(good, refine=31), "refine"), (dict(good, refine=-1), "refine")]:
+        opt = rc.surface_options_struct(bad)
+        st, msg = _status("rc_render_surface", None, C.byref(cam), tf, 256, C.byref(sh),
+                          C.byref(opt), out, None, None)
+        assert st == rc.RC_E_INVALID and word in msg, msg
+    opt = rc.surface_options_struct(good)
+    st, msg = _status("rc_render_surface", None, C.byref(cam), tf, 256, C.byref(sh), C.byref(opt),
+                      out, None, None)
+    assert st == rc.RC_E_INVALID and "volume" in msg

@@ -29,12 +29,16 @@ def _scenes():
              ert=0.95, skip=True),
         dict(seed=46, dims=(9, 9, 9), dtype=np.uint8, image=(3, 130), op="zucker_hummel",
              shading="paper_lambert"),
+        dict(seed=47, dims=(30, 25, 22), dtype=np.uint16, image=(40, 24), op="sobel3d",
+             skip=True, ert=0.98),
     ]
     for sp in specs:
         sc = W.config_small(**sp)
         if sc.shading["model"] == "paper_lambert":
             sc.shading["light_is_point"] = True
             sc.shading["light"] = (40.0, -30.0, 35.0)
+        if sp["seed"] == 47:
+            sc.options.update(nearest=True, ref_step=0.8)
         out.append(sc)
     return out
 

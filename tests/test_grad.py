@@ -32,17 +32,61 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
 
 
-@pytest.mark.parametrize("seed,dtype,ert", [(31, np.float32, 0.0), (32, np.float32, 0.9),
-                                             (33, np.uint8, 0.0), (34, np.uint16, 0.99)])
-def test_adjoint_matches_oracle_small(seed, dtype, ert):
+@pytest.mark.parametrize("seed,dtype,ert,nearest,ref",
+                         [(31, np.float32, 0.0, False, 0.0), (32, np.float32, 0.9, False, 0.0),
+                          (33, np.uint8, 0.0, False, 0.0), (34, np.uint16, 0.99, False, 0.0),
+                          (35, np.float32, 0.0, True, 0.0), (36, np.float32, 0.8, False, 0.35),
+                          (37, np.uint16, 0.0, True, 1.7)])
+def test_adjoint_matches_oracle_small(seed, dtype, ert, nearest, ref):
+    """Also with nearest sampling and with opacity correction."""
     sc = W.config_small(seed=seed, dims=(23, 19, 17), dtype=dtype, image=(35, 27),
                         shading="none", ert=ert)
+    sc.options.update(nearest=nearest, ref_step=ref)
     cam = sc.cameras[0]
     g = np.random.default_rng(seed).normal(size=(cam["height"], cam["width"], 4))
     gv, gt = _gpu_grads(sc, cam, g)
     dv, dt = oracle.render_grad(oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax), cam,
                                 sc.tf, sc.options, g)
     print(f"seed {seed}: rel err volume {_rel(gv, dv):.2e} tf {_rel(gt, dt):.2e}", flush=True)
+    assert np.abs(dv).max() > 0 and np.abs(dt).max() > 0      # not a blank scene
+    assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
+
+
+SHADED = [
+    dict(seed=51, dtype=np.float32, op="central", shading="blinn_phong", nearest=False, ert=0.0),
+    dict(seed=52, dtype=np.uint16, op="sobel3d", shading="blinn_phong", nearest=False, ert=0.95),
+    dict(seed=53, dtype=np.uint8, op="zucker_hummel", shading="paper_lambert", nearest=False,
+         ert=0.0),
+    dict(seed=54, dtype=np.float32, op="sobel3d", shading="paper_lambert", nearest=True, ert=0.0),
+]
+
+
+@pytest.mark.parametrize("case", SHADED, ids=lambda c: f"s{c['seed']}")
+def test_shaded_adjoint_matches_oracle(case):
+    """Reverse mode through Blinn-Phong / the paper's Lambert term, the |G|
+    normalisation and the operator's taps, vs the FP64 adjoint."""
+    sc = W.config_small(seed=case["seed"], dims=(21, 18, 16), dtype=case["dtype"], image=(31, 25),
+                        op=case["op"], shading=case["shading"], ert=case["ert"])
+    if case["shading"] == "paper_lambert":
+        sc.shading["light_is_point"] = True
+        sc.shading["light"] = (40.0, -30.0, 35.0)
+    sc.options.update(nearest=case["nearest"])
+    cam = sc.cameras[0]
+    g = np.random.default_rng(case["seed"]).normal(size=(cam["height"], cam["width"], 4))
+    vol_t = to_dev(sc.volume)
+    h = rc.rc_create_volume(vol_t, sc.spacing, sc.vmin, sc.vmax)
+    tf_t = to_dev(sc.tf)
+    aux = rc.new_aux(cam)
+    rc.rc_render(h, cam, tf_t, sc.shading, sc.options, aux=aux)
+    gv, gt = rc.rc_render_backward(h, cam, tf_t, sc.shading, sc.options, aux,
+                                   to_dev(g.astype(np.float32)))
+    torch.cuda.synchronize()
+    gv, gt = gv.cpu().numpy().astype(np.float64), gt.cpu().numpy().astype(np.float64)
+    dv, dt = oracle.render_grad(oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax), cam,
+                                sc.tf, sc.options, g, shading=sc.shading)
+    print(f"seed {case['seed']}: rel err volume {_rel(gv, dv):.2e} tf {_rel(gt, dt):.2e}",
+          flush=True)
+    assert np.abs(dv).max() > 0 and np.abs(dt).max() > 0
     assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
 
 

@@ -14,9 +14,11 @@ pytestmark = pytest.mark.gpu
 import paper_1609_01317_amd as rc  # noqa: E402
 
 
-def _check(sc, **kw):
+def _check(sc, min_content=20, **kw):
     g = gpu_render(sc, **kw)
     r = oracle_render(sc, **{k: v for k, v in kw.items() if k in ("cam", "options", "shading")})
+    # a scene that shows nothing would pass trivially
+    assert (r["rgba"][..., 3] > 1e-6).sum() >= min_content
     tau = (kw.get("options") or sc.options)["ert_threshold"]
     err, bad = compare(g["rgba"], r, tau)
     print(f"{sc.name}: max err {err:.3e}, failing pixels {int(bad.sum())}", flush=True)
@@ -62,6 +64,23 @@ def test_small_scenes(case):
     _check(sc)
 
 
+VARIANTS = [
+    dict(seed=17, dtype=np.uint8, op="sobel3d", nearest=True, ref=0.0, skip=False),
+    dict(seed=18, dtype=np.uint16, op="central", nearest=False, ref=1.0, skip=True),
+    dict(seed=19, dtype=np.float32, op="zucker_hummel", nearest=True, ref=0.3, skip=False),
+    dict(seed=20, dtype=np.uint16, op="sobel3d", nearest=True, ref=2.0, skip=True),
+]
+
+
+@pytest.mark.parametrize("case", VARIANTS, ids=lambda c: f"s{c['seed']}")
+def test_sampling_variants(case):
+    """Nearest-voxel sampling and opacity correction vs the oracle."""
+    sc = W.config_small(seed=case["seed"], dims=(26, 21, 19), dtype=case["dtype"], image=(37, 29),
+                        op=case["op"], skip=case["skip"], ert=0.97, step=0.45)
+    sc.options.update(nearest=case["nearest"], ref_step=case["ref"])
+    _check(sc)
+
+
 def test_clip_box_and_anisotropic_spacing():
     sc = W.config_small(seed=12, dims=(30, 24, 20), image=(41, 33), op="sobel3d",
                         spacing=(0.8, 1.25, 1.1))
@@ -81,6 +100,34 @@ def test_skip_is_lossless_bitwise():
     assert on["stats"][0] == off["stats"][0]            # same lattice samples
     assert on["stats"][1] < off["stats"][1]             # fewer evaluated
     assert on["stats"][2] == off["stats"][2]            # same non-empty samples
+
+
+@pytest.mark.parametrize("dtype,projection", [(np.uint16, "persp"), (np.uint8, "ortho"),
+                                              (np.float32, "persp")])
+def test_sparse_volume_super_bricks(dtype, projection):
+    """150x130x120 volume (a ragged 5x5x4 grid of 32^3 super-bricks) that is
+    empty except for a few blobs in one corner: long stretches of every ray
+    are cleared by the super-brick test.  Skip on == skip off bit for bit,
+    and the oracle agrees on a pixel sample."""
+    sc = W.config_small(seed=16, dims=(150, 130, 120), dtype=dtype, image=(72, 60),
+                        op="sobel3d", ert=0.99, projection=projection)
+    sc.volume = W.blob_volume((120, 130, 150), 4, seed=16, dtype=dtype, sigma=(3.0, 6.0),
+                              amp=(0.5, 1.0) if dtype == np.float32 else (1500.0, 4000.0)
+                              if dtype == np.uint16 else (120.0, 255.0),
+                              centre_lo=0.65, centre_hi=0.85, normalise=dtype == np.float32)
+    vol = gpu_volume(sc, bricks=True)
+    on = gpu_render(sc, vol=vol, options=dict(sc.options, skip_empty=True), stats=True)
+    off = gpu_render(sc, vol=vol, options=dict(sc.options, skip_empty=False), stats=True)
+    np.testing.assert_array_equal(on["rgba"], off["rgba"])
+    np.testing.assert_array_equal(on["k_last"], off["k_last"])
+    assert on["stats"][0] == off["stats"][0]
+    assert on["stats"][2] == off["stats"][2] > 0
+    assert on["stats"][1] < 0.25 * off["stats"][1]      # most of the lattice skipped
+    H, Wd = 60, 72
+    pix = np.random.default_rng(16).choice(H * Wd, size=600, replace=False)
+    ref = oracle_render(sc, options=dict(sc.options, skip_empty=True), pixels=pix)
+    err, bad = compare(on["rgba"].reshape(-1, 4)[pix], ref, tau=0.99)
+    assert not bad.any(), err
 
 
 def test_ert_bound():
@@ -143,15 +190,15 @@ def test_all_rays_miss_and_tiny_images():
     cam = dict(sc.cameras[0], target=(100.0, 100.0, 100.0))
     g = gpu_render(sc, cam=cam)
     assert np.all(g["rgba"] == 0) and np.all(g["k_last"] == -1)
-    _check(sc)  # 1x1 image through the centre
+    _check(sc, min_content=0)  # 1x1 image through the centre
     sc2 = W.config_small(seed=16, dims=(10, 10, 10), image=(3, 130))
-    _check(sc2)
+    _check(sc2, min_content=0)
 
 
 def test_degenerate_volumes_and_short_tables():
     for dims in [(1, 1, 1), (2, 2, 2), (1, 9, 5), (9, 1, 1)]:
         sc = W.config_small(seed=17, dims=dims, image=(11, 9), dtype=np.float32)
-        _check(sc)
+        _check(sc, min_content=0)
     sc = W.config_small(seed=18, dims=(9, 9, 9), image=(12, 12))
     sc.tf = np.array([[0.2, 0.4, 0.6, 0.0], [0.9, 0.5, 0.1, 0.5]], dtype=np.float32)
     _check(sc)
@@ -183,8 +230,14 @@ def test_error_statuses():
     with pytest.raises(rc.RCError) as e:
         rc.rc_render(vol, sc.cameras[0], tf, dict(sc.shading, grad_eps=0.0), sc.options)
     assert e.value.status == rc.RC_E_INVALID
+    with pytest.raises(rc.RCError) as e:
+        rc.rc_render(vol, sc.cameras[0], tf, sc.shading, dict(sc.options, ref_step=-1.0))
+    assert e.value.status == rc.RC_E_INVALID
     aux = rc.new_aux(sc.cameras[0])
     g = torch.zeros((8, 8, 4), device="cuda")
     with pytest.raises(rc.RCError) as e:
-        rc.rc_render_backward(vol, sc.cameras[0], tf, sc.shading, sc.options, aux, g)
-    assert e.value.status == rc.RC_E_UNSUPPORTED
+        rc.rc_render_backward(vol, sc.cameras[0], tf, sc.shading, sc.options, None, g)
+    assert e.value.status == rc.RC_E_INVALID
+    # every shading model is differentiated
+    rc.rc_render(vol, sc.cameras[0], tf, sc.shading, sc.options, aux=aux)
+    rc.rc_render_backward(vol, sc.cameras[0], tf, sc.shading, sc.options, aux, g)

@@ -346,8 +346,13 @@ def config_small(seed=7, dims=(24, 20, 18), dtype=np.uint8, image=(40, 32), op="
         vol = phantom_volume((nz, ny, nx), 4, seed=seed, dtype=np.uint16)
     else:
         vol = blob_volume((nz, ny, nx), 3, seed=seed, dtype=np.uint8, sigma=(2.0, 6.0))
-    tf = tf_ramps(256 if np.dtype(dtype) != np.uint16 else 4096, seed=seed + 11,
-                  alpha_min=0.02, alpha_max=0.3, lo=0.08, hi=0.9)
+    if np.dtype(dtype) == np.uint16:
+        # breakpoints inside the small phantom's own value range (a few
+        # ellipsoids reach a few hundred to ~1500 of the 12-bit scale)
+        top = max(0.06, 0.9 * float(vol.max()) / 4095.0)
+        tf = tf_ramps(4096, seed=seed + 11, alpha_min=0.02, alpha_max=0.3, lo=0.03, hi=top)
+    else:
+        tf = tf_ramps(256, seed=seed + 11, alpha_min=0.02, alpha_max=0.3, lo=0.08, hi=0.9)
     cam = orbit_camera(dims, spacing, 35.0 + seed, 25.0, image[0], image[1],
                        projection=projection)
     return Scene(f"small_{seed}", vol, tuple(float(s) for s in spacing), vmin, vmax, tf, [cam],
