@@ -97,6 +97,7 @@ struct Ray {
     double o[3], d[3];
     double t_in;
     long long K;        // index of the last lattice sample, -1 on a miss
+    double p0[3], dp[3];    // voxel-space position of sample 0 and step between samples
 };
 
 __device__ inline void setup_ray(const RenderParams& P, const ViewParams& V, int px, int py,
@@ -136,20 +137,24 @@ __device__ inline void setup_ray(const RenderParams& P, const ViewParams& V, int
     R.t_in = tmin;
     R.K = -1;
     if (hit && tmin <= tmax) R.K = (long long)floor((tmax - tmin) / P.step);
+    for (int a = 0; a < 3; ++a) {
+        R.p0[a] = (R.o[a] + tmin * R.d[a]) * P.inv_s[a];
+        R.dp[a] = P.step * R.d[a] * P.inv_s[a];
+    }
 }
 
-// Voxel-space position of the point at ray parameter t (lattice_point: of
-// lattice sample k): cell index and fraction.
+// A voxel-space point split into cell index and fraction (cell_of), for the
+// point at ray parameter t (point_at) or lattice sample k (lattice_point).
 struct Cell {
     int c[3];
     float fr[3];
 };
 
-__device__ __forceinline__ void point_at(const RenderParams& P, const Ray& R, double t, Cell& C,
-                                         double pv[3]) {
+__device__ __forceinline__ void cell_of(const RenderParams& P, const double p3[3], Cell& C,
+                                        double pv[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double p = (R.o[a] + t * R.d[a]) * P.inv_s[a];
+        double p = p3[a];
         pv[a] = p;
         // nearest sampling (Section 3.3, round half up): the cell of the
         // rounded point with fraction 0, so the trilinear and stencil code
@@ -161,9 +166,22 @@ __device__ __forceinline__ void point_at(const RenderParams& P, const Ray& R, do
     }
 }
 
+__device__ __forceinline__ void point_at(const RenderParams& P, const Ray& R, double t, Cell& C,
+                                         double pv[3]) {
+    double p[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = (R.o[a] + t * R.d[a]) * P.inv_s[a];
+    cell_of(P, p, C, pv);
+}
+
+// Lattice sample k: p0 + k dp, one FP64 FMA per axis.  Monotone in k, so
+// the cells of samples between two lattice indices lie between theirs.
 __device__ __forceinline__ void lattice_point(const RenderParams& P, const Ray& R, long long k,
                                               Cell& C, double pv[3]) {
-    point_at(P, R, R.t_in + (double)k * P.step, C, pv);
+    double p[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = fma((double)k, R.dp[a], R.p0[a]);
+    cell_of(P, p, C, pv);
 }
 
 // ---------------------------------------------------------------- voxel sources
@@ -512,6 +530,7 @@ struct Chunk {
     int blo[3], bdim[3];        // brick range of the samples' cells
     unsigned long long live;    // bit set = brick may hold a non-zero-opacity sample
     bool mask_valid;            // live covers every brick of the chunk
+    bool mixed;                 // some sample may sit in an empty brick: test per sample
 };
 
 // One evaluated sample: value, table, and for non-zero opacity the
@@ -555,7 +574,7 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
         Cell C;
         double pv[3];
         lattice_point(P, R, k, C, pv);
-        if (P.skip) {
+        if (ch.mixed) {
             int b0 = clampi(C.c[0], 0, P.nx - 1) >> 3, b1 = clampi(C.c[1], 0, P.ny - 1) >> 3,
                 b2 = clampi(C.c[2], 0, P.nz - 1) >> 3;
             int r0 = b0 - ch.blo[0], r1 = b1 - ch.blo[1], r2 = b2 - ch.blo[2];
@@ -568,10 +587,11 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
             if (empty) continue;
         }
         ++S.evaluated;
-        bool in = staged;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            in = in && C.c[a] - 1 >= ch.lo[a] && C.c[a] + 2 < ch.lo[a] + ch.dim[a];
+        // A lane's cells are monotone along its straight ray (each step of
+        // lattice_point is a monotone rounding), so its samples S.k..kstop lie
+        // between the two end cells that chunk_cells reduced into the box:
+        // a staged chunk's samples always read the box.
+        const bool in = staged;
         S.direct += in ? 0u : 1u;
         bool term = in ? shade_sample<VT, OP>(P, lsrc, C, pv, rs, S)
                        : shade_sample<VT, OP>(P, gsrc, C, pv, rs, S);
@@ -597,7 +617,8 @@ __device__ __forceinline__ bool chunk_cells(const RenderParams& P, const Ray& R,
     kstop = -1;
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
     if (active) {
-        double q = ceil((tau_end - R.t_in) / P.step) - 1.0;
+        // which samples fall in a chunk only groups the work: any rounding here is harmless
+        double q = ceil((tau_end - R.t_in) * P.inv_step) - 1.0;
         kstop = q < (double)R.K ? (long long)fmax(q, -1.0) : R.K;
         // the lane(s) defining tau always own at least their next sample
         if (R.t_in + (double)k * P.step < tau_end && kstop < k) kstop = k;
@@ -722,6 +743,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
         }
         // brick occupancy of the chunk: one brick per lane, one ballot
         ch.live = ~0ull;
+        ch.mixed = P.skip && !ch.mask_valid;
         if (P.skip && ch.mask_valid) {
             int nbr = ch.bdim[0] * ch.bdim[1] * ch.bdim[2];
             bool live = false;
@@ -732,6 +754,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
                 live = P.empty[b] == 0;
             }
             ch.live = __ballot(live);
+            ch.mixed = ch.live != (nbr == 64 ? ~0ull : ((1ull << nbr) - 1ull));
             if (ch.live == 0ull) {              // every sample of the chunk has alpha 0
                 ++n_empty;
                 if (active && kstop >= S.k) S.k = kstop + 1;
@@ -778,7 +801,7 @@ __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, i
     Ray R;
     R.K = -1;
     R.t_in = 0.0;
-    for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = 0.0;
+    for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = R.p0[a] = R.dp[a] = 0.0;
     if (valid) setup_ray(P, V, px, py, R);
     MarchOut M;
     march_wave<VT, OP>(P, R, valid, lds, lane, M);

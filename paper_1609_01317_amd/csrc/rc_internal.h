@@ -76,6 +76,7 @@ struct RenderParams {
     double lo[3], hi[3];
     double step;
     double inv_s[3];
+    double inv_step;            // 1 / step (chunk extents only; the lattice uses step)
     float s[3];
     // volume (bricked)
     const void* vox;

@@ -325,6 +325,7 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     fill_view(P.view, cam);
     sampling_box(v, opt, P.lo, P.hi);
     P.step = opt->step;
+    P.inv_step = 1.0 / opt->step;
     for (int a = 0; a < 3; ++a) {
         P.inv_s[a] = 1.0 / v->spacing[a];
         P.s[a] = (float)v->spacing[a];
