@@ -49,9 +49,28 @@ struct MinOp { __device__ int operator()(int a, int b) const { return min(a, b);
 struct MaxOp { __device__ int operator()(int a, int b) const { return max(a, b); } };
 __device__ __forceinline__ int wave_min(int v) { return wave_reduce_dpp(v, INT_MAX, MinOp()); }
 __device__ __forceinline__ int wave_max(int v) { return wave_reduce_dpp(v, INT_MIN, MaxOp()); }
-__device__ __forceinline__ double wave_min(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
+// Minimum of non-negative doubles (+inf allowed), exact: their bit patterns
+// order like unsigned 64-bit integers, so the same DPP steps run on both
+// halves with a 64-bit compare (no LDS permutes).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    const int ones = -1;    // identity of the minimum in lanes the move does not write
+    unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(ones, (int)(unsigned)v, CTRL, ROWS, 0xF, false);
+    unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp(ones, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xF, false);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double wave_min_nonneg(double x) {
+    unsigned long long v = (unsigned long long)__double_as_longlong(x);
+    v = min(v, dpp_u64<0xB1, 0xF>(v));     // quad_perm 1,0,3,2
+    v = min(v, dpp_u64<0x4E, 0xF>(v));     // quad_perm 2,3,0,1
+    v = min(v, dpp_u64<0x141, 0xF>(v));    // row_half_mirror
+    v = min(v, dpp_u64<0x140, 0xF>(v));    // row_mirror
+    v = min(v, dpp_u64<0x142, 0xA>(v));    // row_bcast:15
+    v = min(v, dpp_u64<0x143, 0xC>(v));    // row_bcast:31
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -696,12 +715,17 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     int len = kChunkInit;
     // a super-chunk is tried at the start and after every empty chunk
     bool try_super = P.skip && P.super_empty != nullptr;
+    // Every chunk advances at least the lane that owns the earliest pending
+    // sample, so 64 (K_max + 1) chunks finish any wave; the cap only turns a
+    // broken invariant into a wrong image instead of a wave that never ends.
+    const long long chunk_cap = 64ll * (wave_max(has_ray ? (int)R.K : -1) + 2);
+    long long n_chunks = 0;
     for (;;) {
         bool active = !S.done && S.k <= R.K;
         if (!active) S.done = true;
-        if (__ballot(active) == 0ull) break;
+        if (__ballot(active) == 0ull || ++n_chunks > chunk_cap) break;
         // the chunk starts at the earliest pending sample of the wave
-        double tau = wave_min(active ? R.t_in + (double)S.k * P.step : INFINITY);
+        double tau = wave_min_nonneg(active ? R.t_in + (double)S.k * P.step : INFINITY);
         Chunk ch;
         long long kstop = -1;
         if (try_super) {
