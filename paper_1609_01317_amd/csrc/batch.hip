@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void batch_super(const MaskJob* __restrict__ j
 
 // The persistent kernel.  `kind` = dtype * 3 + gradient operator selects the
 // instantiation per work unit (uniform across the wave).
-__global__ __launch_bounds__(256) void raycast_batch(const RenderParams* __restrict__ items,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void raycast_batch(const RenderParams* __restrict__ items,
                                                      const int* __restrict__ kinds,
                                                      const int* __restrict__ tile_off,
                                                      const int* __restrict__ order, int n,

@@ -692,6 +692,42 @@ __device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const R
     }
 }
 
+// First lattice index of this lane's ray that may lie in a non-empty
+// super-brick: a 3D DDA over the 32^3 super-brick grid along the ray in
+// voxel space (p = p0 + k dp, k in lattice units), stopping at the first
+// super-brick whose flag is clear.  The start cell comes from the FP64
+// position; the crossings are stepped in FP32 (relative error ~1e-7 of k,
+// k < 2^24), and every sample before the returned index lies at least two
+// lattice steps before the crossing, so no rounding puts it into a
+// non-empty super-brick.  Those samples have opacity 0 and are skipped.
+// Returns K + 1 when the whole ray is empty.
+__device__ __forceinline__ long long entry_index(const RenderParams& P, const Ray& R) {
+    const int n[3] = {P.nx, P.ny, P.nz}, ns[3] = {P.nsx, P.nsy, P.nsz};
+    int cell[3], dir[3];
+    float kb[3], dk[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cell[a] = clampi((int)floor(R.p0[a]), 0, n[a] - 1) >> 5;
+        const float d = (float)R.dp[a];
+        dir[a] = d > 0.0f ? 1 : (d < 0.0f ? -1 : 0);
+        const float bound = (float)(cell[a] + (d > 0.0f ? 1 : 0)) * 32.0f;
+        dk[a] = dir[a] != 0 ? 32.0f / fabsf(d) : INFINITY;
+        kb[a] = dir[a] != 0 ? (bound - (float)R.p0[a]) / d : INFINITY;
+    }
+    float k_enter = 0.0f;
+    const float kmax = (float)R.K;
+#pragma unroll 1
+    for (int it = 0; it < ns[0] + ns[1] + ns[2]; ++it) {
+        if (P.super_empty[(cell[2] * P.nsy + cell[1]) * P.nsx + cell[0]] == 0) break;
+        int a = kb[0] <= kb[1] ? (kb[0] <= kb[2] ? 0 : 2) : (kb[1] <= kb[2] ? 1 : 2);
+        k_enter = kb[a];
+        cell[a] += dir[a];
+        if (!(k_enter <= kmax) || cell[a] < 0 || cell[a] >= ns[a]) return R.K + 1;
+        kb[a] += dk[a];
+    }
+    return max(0ll, (long long)floorf(k_enter) - 2);
+}
+
 // March the 64 rays of this wave together.  `has_ray` is false for lanes
 // outside the image; they still take part in the wave-wide steps.
 template <typename VT, int OP>
@@ -704,6 +740,8 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     S.k_term = -1;
     S.done = !has_ray || R.K < 0;
     S.evaluated = S.shaded = S.direct = 0;
+    // leading empty space: each lane jumps over its empty super-bricks
+    if (!S.done && P.skip && P.super_empty != nullptr) S.k = entry_index(P, R);
     unsigned n_staged = 0, n_empty = 0, n_direct = 0;
     // Staging pays off when samples need the stencil neighbourhood; an
     // unshaded march reads 8 voxels per sample and gathers them directly.

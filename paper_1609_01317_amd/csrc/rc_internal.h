@@ -103,7 +103,7 @@ struct RenderParams {
     float ocorr;                // opacity-correction exponent step / ref_step, 0 = off
     const uint8_t* empty;       // per-brick flag, 1 = every sample has alpha 0
     const uint8_t* super_empty; // per-super-brick flag (4x4x4 bricks), or null
-    int nsx, nsy;               // super-bricks per row / per slab row
+    int nsx, nsy, nsz;          // super-bricks per axis
     rc_stats* stats;            // kStatSlots consecutive copies, or null
 };
 

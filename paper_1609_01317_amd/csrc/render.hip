@@ -95,8 +95,11 @@ size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
 
 // ---------------------------------------------------------------- the kernel
 // Workgroup = one wave = one pixel tile, placed by tile_of_block.
+// Three resident waves per SIMD: the register allocator keeps the march
+// within 168 VGPRs.
 template <typename VT, int OP>
-__global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void raycast_fwd(
+    RenderParams P) {
     __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
     const ViewParams& V = P.view;
     int tile = tile_of_block(blockIdx.x, V.tiles_x, V.n_tiles / V.tiles_x);
@@ -106,7 +109,8 @@ __global__ __launch_bounds__(64) void raycast_fwd(RenderParams P) {
 // Several views of one volume: each view owns a run of blocks (a multiple of
 // the XCD group size, so the group dealing above holds inside every view).
 template <typename VT, int OP>
-__global__ __launch_bounds__(64) void raycast_views(RenderParams P, ViewSet S) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void raycast_views(
+    RenderParams P, ViewSet S) {
     __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
     int b = blockIdx.x, v = 0;
     while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
@@ -364,6 +368,7 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     P.super_empty = nullptr;
     P.nsx = v->nsx;
     P.nsy = v->nsy;
+    P.nsz = v->nsz;
     P.stats = nullptr;
 }
 
