@@ -231,11 +231,13 @@ struct LdsSrc {
     int bx, bxy;        // row and slab strides in elements
     __device__ __forceinline__ void offsets(const Cell& C, int ox[4], int oy[4], int oz[4]) const {
         int x0 = C.c[0] - 1 - lo[0], y0 = C.c[1] - 1 - lo[1], z0 = C.c[2] - 1 - lo[2];
+        // box coordinates and strides are far below 2^23: 24-bit multiplies
+        const int yb = __mul24(y0, bx), zb = __mul24(z0, bxy);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             ox[i] = x0 + i;
-            oy[i] = (y0 + i) * bx;
-            oz[i] = (z0 + i) * bxy;
+            oy[i] = yb + i * bx;
+            oz[i] = zb + i * bxy;
         }
     }
 };
