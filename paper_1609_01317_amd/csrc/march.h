@@ -246,11 +246,13 @@ struct LdsSrc {
 // Trilinear interpolation as 7 lerps, x then y then z (Section 3.4, eq. 2).
 template <typename VT>
 __device__ __forceinline__ float sample_value(const VT* base, const int ox[4], const int oy[4],
-                                              const int oz[4], const Cell& C) {
-    float v000 = (float)base[ox[1] + oy[1] + oz[1]], v100 = (float)base[ox[2] + oy[1] + oz[1]];
-    float v010 = (float)base[ox[1] + oy[2] + oz[1]], v110 = (float)base[ox[2] + oy[2] + oz[1]];
-    float v001 = (float)base[ox[1] + oy[1] + oz[2]], v101 = (float)base[ox[2] + oy[1] + oz[2]];
-    float v011 = (float)base[ox[1] + oy[2] + oz[2]], v111 = (float)base[ox[2] + oy[2] + oz[2]];
+                                              const int oz[4], const Cell& C, float corner[8]) {
+    // corner[(z-1)*4 + (y-1)*2 + (x-1)] = voxel (x, y, z) of the 4x4x4 footprint
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        corner[q] = (float)base[ox[1 + (q & 1)] + oy[1 + ((q >> 1) & 1)] + oz[1 + (q >> 2)]];
+    const float v000 = corner[0], v100 = corner[1], v010 = corner[2], v110 = corner[3];
+    const float v001 = corner[4], v101 = corner[5], v011 = corner[6], v111 = corner[7];
     float i1 = lerpf(v000, v100, C.fr[0]);
     float i2 = lerpf(v010, v110, C.fr[0]);
     float i3 = lerpf(v001, v101, C.fr[0]);
@@ -258,6 +260,13 @@ __device__ __forceinline__ float sample_value(const VT* base, const int ox[4], c
     float i5 = lerpf(i1, i2, C.fr[1]);
     float i6 = lerpf(i3, i4, C.fr[1]);
     return lerpf(i5, i6, C.fr[2]);
+}
+
+template <typename VT>
+__device__ __forceinline__ float sample_value(const VT* base, const int ox[4], const int oy[4],
+                                              const int oz[4], const Cell& C) {
+    float corner[8];
+    return sample_value<VT>(base, ox, oy, oz, C, corner);
 }
 
 // Lookup table (Section 3.7): u = clamp((v-vmin)/(vmax-vmin),0,1)*(M-1),
@@ -333,10 +342,10 @@ __device__ __forceinline__ void axis_taps(float t, AxisTaps& k) {
     k.A[3] = a1 * w1;
 }
 
-template <typename VT, int OP>
+template <typename VT, int OP, bool HAVE_CORNERS = false>
 __device__ __forceinline__ void gradient(const RenderParams& P, const VT* base, const int ox[4],
                                          const int oy[4], const int oz[4], const Cell& C,
-                                         float g[3]) {
+                                         float g[3], const float* corner = nullptr) {
     constexpr bool SEP = OpTaps<OP>::kSep;
     AxisTaps kx, ky, kz;
     axis_taps<OP>(C.fr[0], kx);
@@ -350,7 +359,12 @@ __device__ __forceinline__ void gradient(const RenderParams& P, const VT* base, 
         for (int y = 0; y < 4; ++y) {
             float v[4];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) v[x] = (float)base[ox[x] + oy[y] + oz[z]];
+            for (int x = 0; x < 4; ++x) {
+                // the cell's own 8 voxels were read for the value already
+                const bool inner = (x == 1 || x == 2) && (y == 1 || y == 2) && (z == 1 || z == 2);
+                v[x] = (HAVE_CORNERS && inner) ? corner[(z - 1) * 4 + (y - 1) * 2 + (x - 1)]
+                                               : (float)base[ox[x] + oy[y] + oz[z]];
+            }
             rowD[y] = dot4(kx.D, v);
             rowL[y] = fmaf(kx.L[2], v[2], kx.L[1] * v[1]);
             rowA[y] = SEP ? dot4(kx.A, v) : 0.f;
@@ -562,7 +576,8 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
                                              LaneState& S) {
     int ox[4], oy[4], oz[4];
     src.offsets(C, ox, oy, oz);
-    float v = sample_value<VT>(src.base, ox, oy, oz, C);
+    float corner[8];
+    float v = sample_value<VT>(src.base, ox, oy, oz, C, corner);
     float4 rgba = tf_lookup(P, v);
     float a = rgba.w;
     if (a == 0.0f) return false;
@@ -571,7 +586,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     float c[3] = {rgba.x, rgba.y, rgba.z};
     if (P.shade != RC_SHADE_NONE) {
         float g[3];
-        gradient<VT, OP>(P, src.base, ox, oy, oz, C, g);
+        gradient<VT, OP, true>(P, src.base, ox, oy, oz, C, g, corner);
         shade(P, rgba, g, pv, rs, c);
     }
     float ta = S.T * a;
