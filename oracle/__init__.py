@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 OP = {"central": 0, "sobel3d": 1, "zucker_hummel": 2}
 SHADE = {"none": 0, "blinn_phong": 1, "paper_lambert": 2}
-FLAG_HIT, FLAG_TIE, FLAG_ERT_NEAR, FLAG_ISO_NEAR = 1, 2, 4, 8
+FLAG_HIT, FLAG_TIE, FLAG_ERT_NEAR, FLAG_ISO_NEAR, FLAG_ADAPT_NEAR = 1, 2, 4, 8, 16
 
 
 def build(force: bool = True) -> str:
@@ -54,7 +54,7 @@ class _Shading(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("step", C.c_double), ("gradient_op", C.c_int), ("ert_threshold", C.c_double),
                 ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3), ("nearest", C.c_int),
-                ("ref_step", C.c_double)]
+                ("ref_step", C.c_double), ("adapt_factor", C.c_int), ("adapt_range", C.c_double)]
 
 
 class _SurfaceOptions(C.Structure):
@@ -132,7 +132,8 @@ def _shading(sh):
 def _options(opt):
     return _Options(opt["step"], OP[opt["gradient_op"]], opt["ert_threshold"],
                     (C.c_double * 3)(*opt["clip_lo"]), (C.c_double * 3)(*opt["clip_hi"]),
-                    int(bool(opt.get("nearest", False))), float(opt.get("ref_step", 0.0)))
+                    int(bool(opt.get("nearest", False))), float(opt.get("ref_step", 0.0)),
+                    int(opt.get("adapt_factor", 0)), float(opt.get("adapt_range", 0.0)))
 
 
 def sample(vol: Volume, p):

@@ -387,12 +387,101 @@ static void march(const orc_volume* v, const double* tf, int M, const orc_shadin
     *t_final = T;
 }
 
+/* ------------------------------------------------------------------ */
+/* Adaptive sampling (Section 5.2: detail-poor regions are sampled at a */
+/* lower rate, detail-rich ones at the full rate).  Reading: the regions */
+/* are the 8^3 bricks of the empty-space grid; a brick is detail-poor    */
+/* when the range of the voxels its samples can touch (the brick plus    */
+/* its one-voxel high apron) is at most adapt_range.  A sample in a poor */
+/* brick advances the ray by adapt_factor steps, any other by one; each  */
+/* sample's opacity is corrected to the distance it stands for           */
+/* (a = 1 - (1 - a_tf)^(d / ref), ref = ref_step or the base step), so a */
+/* homogeneous region keeps its opacity.  Samples are taken while        */
+/* t <= t_out; t accumulates in FP64.                                    */
+/* ------------------------------------------------------------------ */
+static unsigned char* poor_bricks(const orc_volume* v, double range) {
+    long nbx = (v->nx + 7) / 8, nby = (v->ny + 7) / 8, nbz = (v->nz + 7) / 8;
+    unsigned char* poor = (unsigned char*)malloc((size_t)(nbx * nby * nbz));
+    if (!poor) return NULL;
+    for (long bz = 0; bz < nbz; ++bz)
+        for (long by = 0; by < nby; ++by)
+            for (long bx = 0; bx < nbx; ++bx) {
+                double lo = INFINITY, hi = -INFINITY;
+                for (long z = 8 * bz; z <= 8 * bz + 8; ++z)
+                    for (long y = 8 * by; y <= 8 * by + 8; ++y)
+                        for (long x = 8 * bx; x <= 8 * bx + 8; ++x) {
+                            double val = voxel(v, x, y, z);
+                            if (val < lo) lo = val;
+                            if (val > hi) hi = val;
+                        }
+                poor[(bz * nby + by) * nbx + bx] = (hi - lo) <= range;
+            }
+    return poor;
+}
+
+static void march_adaptive(const orc_volume* v, const double* tf, int M, const orc_shading* sh,
+                           const orc_options* opt, const ray_setup* rs, const unsigned char* poor,
+                           double t_end, double out[4], int* k_last, double* t_final,
+                           int* ert_near, int* adapt_near, double* t_tie) {
+    const long nbx = (v->nx + 7) / 8, nby = (v->ny + 7) / 8;
+    const long n[3] = {v->nx, v->ny, v->nz};
+    const double ref = opt->ref_step > 0.0 ? opt->ref_step : opt->step;
+    double C[3] = {0, 0, 0}, T = 1.0, t = rs->t_in;
+    long j = 0, last = -1;
+    *t_tie = NAN;
+    while (t <= t_end) {
+        if (fabs(t - rs->t_out) < ORC_TIE_EPS * opt->step) *t_tie = t;
+        double pv[3], pw[3];
+        long b[3];
+        for (int a = 0; a < 3; ++a) {
+            pw[a] = rs->o[a] + t * rs->d[a];
+            pv[a] = pw[a] / v->spacing[a];
+            long c = (long)floor(pv[a]);
+            b[a] = clampl(c, n[a]) / 8;
+            double r = pv[a] - 8.0 * floor(pv[a] / 8.0 + 0.5);   /* distance to a brick plane */
+            if (fabs(r) < ORC_ADAPT_EPS && pv[a] > 0.5 && pv[a] < (double)n[a] - 1.5) *adapt_near = 1;
+        }
+        int is_poor = poor[(b[2] * nby + b[1]) * nbx + b[0]];
+        double step = is_poor ? (double)opt->adapt_factor * opt->step : opt->step;
+        /* one sample, as in eval_sample, with the opacity corrected to `step` */
+        double pr[3];
+        for (int a = 0; a < 3; ++a) pr[a] = opt->nearest ? floor(pv[a] + 0.5) : pv[a];
+        double val = opt->nearest ? orc_sample_nearest(v, pv) : orc_sample(v, pv);
+        int interior;
+        double u = value_to_u(v, val, M, &interior), rgba[4], c[3];
+        orc_tf(tf, M, u, rgba);
+        double a = rgba[3];
+        if (a != 0.0 && step != ref) a = 1.0 - pow(1.0 - a, step / ref);
+        if (sh->model == ORC_SHADE_NONE || a == 0.0) {
+            c[0] = rgba[0]; c[1] = rgba[1]; c[2] = rgba[2];
+        } else {
+            double g[3];
+            orc_gradient(v, opt->gradient_op, pr, g, NULL);
+            orc_shade(sh, rgba, g, pw, rs->d, c);
+        }
+        for (int ch = 0; ch < 3; ++ch) C[ch] += T * a * c[ch];
+        T *= (1.0 - a);
+        last = j;
+        if (opt->ert_threshold > 0.0) {
+            if (fabs((1.0 - T) - opt->ert_threshold) < ORC_ERT_EPS) *ert_near = 1;
+            if (1.0 - T >= opt->ert_threshold) break;
+        }
+        t += step;
+        ++j;
+    }
+    if (fabs(t - rs->t_out) < ORC_TIE_EPS * opt->step && last + 1 == j) *t_tie = t;
+    out[0] = C[0]; out[1] = C[1]; out[2] = C[2]; out[3] = 1.0 - T;
+    *k_last = (int)last;
+    *t_final = T;
+}
+
 static int check_args(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
                       const orc_options* opt) {
     if (!v || !v->data || !cam || !tf || !opt) return -1;
     if (v->nx < 1 || v->ny < 1 || v->nz < 1 || M < 2) return -1;
     if (!(opt->step > 0.0) || !(v->vmax > v->vmin)) return -1;
     if (!(opt->ref_step >= 0.0) || isinf(opt->ref_step)) return -1;
+    if (opt->adapt_factor < 0 || opt->adapt_factor > 64 || isnan(opt->adapt_range)) return -1;
     if (cam->width < 1 || cam->height < 1) return -1;
     return 0;
 }
@@ -404,6 +493,9 @@ int orc_render(const orc_volume* v, const orc_camera* cam, const double* tf, int
     if (check_args(v, cam, tf, M, opt) || !sh || !rgba) return -1;
     long total = (long)cam->width * cam->height;
     if (!pix) n = total;
+    const int adaptive = opt->adapt_factor > 1;
+    unsigned char* poor = adaptive ? poor_bricks(v, opt->adapt_range) : NULL;
+    if (adaptive && !poor) return -1;
 #ifdef _OPENMP
     if (threads > 0) omp_set_num_threads(threads);
 #else
@@ -416,19 +508,38 @@ int orc_render(const orc_volume* v, const orc_camera* cam, const double* tf, int
         ray_setup rs;
         setup_ray(v, cam, opt, px, py, &rs);
         double out[4] = {0, 0, 0, 0}, alt[4] = {0, 0, 0, 0};
-        int kl = -1, kl_alt = -1, near = 0, near_alt = 0;
+        int kl = -1, kl_alt = -1, near = 0, near_alt = 0, anear = 0, tie = rs.tie;
         double tf_ = 1.0, tf_alt = 1.0;
-        if (rs.K >= 0) march(v, tf, M, sh, opt, &rs, rs.K, out, &kl, &tf_, &near);
-        if (rs.tie && rs.K_alt >= 0)
-            march(v, tf, M, sh, opt, &rs, rs.K_alt, alt, &kl_alt, &tf_alt, &near_alt);
+        if (adaptive) {
+            /* the adaptive march has its own end rule: a sample within
+             * ORC_TIE_EPS steps of t_out may or may not be taken */
+            double t_tie = NAN, t_tie2;
+            if (rs.hit) {
+                march_adaptive(v, tf, M, sh, opt, &rs, poor, rs.t_out, out, &kl, &tf_, &near,
+                               &anear, &t_tie);
+                memcpy(alt, out, sizeof out);
+            }
+            tie = !isnan(t_tie);
+            if (tie) {
+                double end = t_tie <= rs.t_out ? nextafter(t_tie, -INFINITY) : t_tie;
+                march_adaptive(v, tf, M, sh, opt, &rs, poor, end, alt, &kl_alt, &tf_alt,
+                               &near_alt, &anear, &t_tie2);
+            }
+        } else {
+            if (rs.K >= 0) march(v, tf, M, sh, opt, &rs, rs.K, out, &kl, &tf_, &near);
+            if (rs.tie && rs.K_alt >= 0)
+                march(v, tf, M, sh, opt, &rs, rs.K_alt, alt, &kl_alt, &tf_alt, &near_alt);
+        }
         memcpy(rgba + q * 4, out, sizeof out);
-        if (rgba_alt) memcpy(rgba_alt + q * 4, rs.tie ? alt : out, sizeof out);
+        if (rgba_alt) memcpy(rgba_alt + q * 4, tie ? alt : out, sizeof out);
         if (flags)
-            flags[q] = (rs.K >= 0 ? ORC_FLAG_HIT : 0) | (rs.tie ? ORC_FLAG_LATTICE_TIE : 0) |
-                       ((near || near_alt) ? ORC_FLAG_ERT_NEAR : 0);
+            flags[q] = (rs.hit ? ORC_FLAG_HIT : 0) | (tie ? ORC_FLAG_LATTICE_TIE : 0) |
+                       ((near || near_alt) ? ORC_FLAG_ERT_NEAR : 0) |
+                       (anear ? ORC_FLAG_ADAPT_NEAR : 0);
         if (k_last) k_last[q] = kl;
         if (t_final) t_final[q] = tf_;
     }
+    free(poor);
     return 0;
 }
 
@@ -540,6 +651,7 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
                     const orc_shading* sh_in, const orc_options* opt, const long* pix, long n,
                     const double* g_rgba, double* dvol, double* dtf) {
     if (check_args(v, cam, tf, M, opt) || !g_rgba || !dvol || !dtf) return -1;
+    if (opt->adapt_factor > 1) return -1;      /* the reverse mode follows the fixed lattice */
     orc_shading none;
     memset(&none, 0, sizeof none);
     none.model = ORC_SHADE_NONE;

@@ -43,12 +43,16 @@ enum {
     ORC_FLAG_LATTICE_TIE = 2,/* (t_out-t_in)/step within ORC_TIE_EPS of an integer:
                                 rgba_alt holds the result with the other sample count */
     ORC_FLAG_ERT_NEAR = 4,   /* 1-T came within ORC_ERT_EPS of the ERT threshold */
-    ORC_FLAG_ISO_NEAR = 8    /* surface mode: a window test that decided the result had a
+    ORC_FLAG_ISO_NEAR = 8,   /* surface mode: a window test that decided the result had a
                                 value within ORC_ISO_EPS*(vmax-vmin) of a window bound */
+    ORC_FLAG_ADAPT_NEAR = 16 /* adaptive sampling: a sample lay within ORC_ADAPT_EPS voxels
+                                of a brick boundary, where the brick (and so the step) taken
+                                depends on rounding */
 };
 #define ORC_TIE_EPS 1e-6
 #define ORC_ERT_EPS 1e-4
 #define ORC_ISO_EPS 1e-6
+#define ORC_ADAPT_EPS 1e-7
 
 typedef struct {
     const double* data;      /* [nz][ny][nx] voxel values, x fastest */
@@ -80,6 +84,10 @@ typedef struct {
     double clip_lo[3], clip_hi[3]; /* clip box in world units, intersected with the volume box */
     int nearest;             /* 1: nearest-voxel sampling (Section 3.3's rounding) */
     double ref_step;         /* > 0: opacity correction to this reference step; 0: off */
+    int adapt_factor;        /* > 1: adaptive sampling (Section 5.2): samples in 8^3 bricks
+                                whose value range is at most adapt_range advance by
+                                adapt_factor * step; 0 or 1: off */
+    double adapt_range;      /* raw-value range up to which a brick counts as detail-poor */
 } orc_options;
 
 /* trilinear sample at a voxel-space point (Section 3.4) */

@@ -301,3 +301,73 @@ def render_surface(vol_zyx, spacing, vmin, vmax, tf, cam, sh, opt, pixels=None):
         out.append(np.concatenate([rgb, [1.0]]))
         th.append(t)
     return np.array(out).reshape(-1, 4), np.array(th)
+
+
+# ---------------------------------------------------------------- adaptive sampling
+def poor_brick_flags(vol_zyx, adapt_range):
+    """Detail-poor flags of the 8^3 bricks: value range over the brick plus
+    its one-voxel high apron (edge-replicated), via numpy slicing."""
+    v = np.asarray(vol_zyx, dtype=np.float64)
+    nz, ny, nx = v.shape
+    nbz, nby, nbx = (nz + 7) // 8, (ny + 7) // 8, (nx + 7) // 8
+    pad = np.pad(v, ((0, 8 * nbz + 1 - nz), (0, 8 * nby + 1 - ny), (0, 8 * nbx + 1 - nx)),
+                 mode="edge")
+    flags = np.zeros((nbz, nby, nbx), dtype=bool)
+    for bz in range(nbz):
+        for by in range(nby):
+            for bx in range(nbx):
+                blk = pad[8 * bz:8 * bz + 9, 8 * by:8 * by + 9, 8 * bx:8 * bx + 9]
+                flags[bz, by, bx] = blk.max() - blk.min() <= adapt_range
+    return flags
+
+
+def render_adaptive(vol_zyx, spacing, vmin, vmax, tf, cam, sh, opt, pixels=None):
+    """rgba [n,4] of the adaptive march, written as a list of (t, step)
+    pairs built first and composited afterwards (front to back)."""
+    g = Grid(vol_zyx, spacing, vmin, vmax)
+    flags = poor_brick_flags(vol_zyx, opt["adapt_range"])
+    tf = np.asarray(tf, dtype=np.float64)
+    M = tf.shape[0]
+    ent = np.arange(M, dtype=np.float64)
+    W, H = cam["width"], cam["height"]
+    ext = (np.array([g.nx, g.ny, g.nz]) - 1) * g.s
+    lo = np.maximum(np.asarray(opt["clip_lo"]), 0.0)
+    hi = np.minimum(np.asarray(opt["clip_hi"]), ext)
+    ref = opt.get("ref_step", 0.0) or opt["step"]
+    m = opt["adapt_factor"]
+    ids = range(W * H) if pixels is None else pixels
+    out = []
+    for pid in ids:
+        px, py = pid % W, pid // W
+        o, d = pixel_ray(cam, px, py)
+        span = box_span(o, d, lo, hi) if np.all(lo <= hi) else None
+        plan = []
+        if span is not None:
+            t = span[0]
+            while t <= span[1]:
+                pv = (o + t * d) / g.s
+                b = [min(max(int(math.floor(c)), 0), n - 1) // 8
+                     for c, n in zip(pv, (g.nx, g.ny, g.nz))]
+                step = m * opt["step"] if flags[b[2], b[1], b[0]] else opt["step"]
+                plan.append((t, step))
+                t += step
+        C, T = np.zeros(3), 1.0
+        for t, step in plan:
+            pw = o + t * d
+            pv = pw / g.s
+            val = g.sample(pv)
+            u = min(max((val - vmin) / (vmax - vmin), 0.0), 1.0) * (M - 1)
+            rgba = np.array([np.interp(u, ent, tf[:, c]) for c in range(4)])
+            a = rgba[3]
+            if 0.0 < a < 1.0:
+                a = -math.expm1(math.log1p(-a) * step / ref)
+            col = rgba[:3]
+            if sh["model"] != "none" and a != 0.0:
+                grad, _ = g.gradient(opt["gradient_op"], pv)
+                col = shade(sh, rgba, grad, pw, d)
+            C = C + T * a * np.asarray(col)
+            T *= 1.0 - a
+            if opt["ert_threshold"] > 0 and 1.0 - T >= opt["ert_threshold"]:
+                break
+        out.append(np.concatenate([C, [1.0 - T]]))
+    return np.array(out).reshape(-1, 4)

@@ -238,11 +238,12 @@ def default_shading(model="blinn_phong", light=(-0.4, -0.5, 0.75), light_is_poin
 
 def default_options(step=0.5, gradient_op="central", ert_threshold=0.0, skip_empty=False,
                     clip_lo=(-1e30, -1e30, -1e30), clip_hi=(1e30, 1e30, 1e30), nearest=False,
-                    ref_step=0.0):
+                    ref_step=0.0, adapt_factor=0, adapt_range=0.0):
     return {"step": float(step), "gradient_op": gradient_op, "ert_threshold": float(ert_threshold),
             "skip_empty": bool(skip_empty), "clip_lo": tuple(float(v) for v in clip_lo),
             "clip_hi": tuple(float(v) for v in clip_hi), "nearest": bool(nearest),
-            "ref_step": float(ref_step)}
+            "ref_step": float(ref_step), "adapt_factor": int(adapt_factor),
+            "adapt_range": float(adapt_range)}
 
 
 def default_surface_options(step=2.0, gradient_op="central", iso_lo=0.0, iso_hi=1e30, refine=6,
