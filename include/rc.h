@@ -103,6 +103,15 @@ typedef struct {
                                  on the voxel nearest to the sample point */
     float opacity_ref_step;   /* 0: off; > 0: table opacities are per this sample distance and
                                  are corrected to `step`: a = 1 - (1 - a_tf)^(step / ref) */
+    int32_t adapt_factor;     /* 0 or 1: fixed step.  2..64: adaptive sampling (Section 5.2):
+                                 a sample in an 8^3 brick whose value range (rc_build_bricks)
+                                 is at most adapt_range advances the ray by adapt_factor steps,
+                                 any other by one; each sample's opacity is corrected to the
+                                 distance it stands for, relative to opacity_ref_step or, if
+                                 that is 0, to `step`.  Samples are taken while t <= t_out.
+                                 Needs rc_build_bricks; rc_render only (batched, multi-view and
+                                 reverse calls return RC_E_UNSUPPORTED). */
+    float adapt_range;        /* raw-value range up to which a brick counts as detail-poor */
 } rc_options;
 
 /* Optional per-render counters, accumulated (+=) with device atomics. */

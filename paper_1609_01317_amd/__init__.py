@@ -56,7 +56,8 @@ class rc_options(C.Structure):
     _fields_ = [("step", C.c_double), ("clip_lo", C.c_double * 3), ("clip_hi", C.c_double * 3),
                 ("ert_threshold", C.c_float), ("gradient_op", C.c_int32),
                 ("skip_empty", C.c_int32), ("reserved", C.c_int32), ("sampling", C.c_int32),
-                ("opacity_ref_step", C.c_float)]
+                ("opacity_ref_step", C.c_float), ("adapt_factor", C.c_int32),
+                ("adapt_range", C.c_float)]
 
 
 class rc_surface_options(C.Structure):
@@ -191,7 +192,8 @@ def options_struct(opt: dict) -> rc_options:
     return rc_options(float(opt["step"]), (C.c_double * 3)(*opt["clip_lo"]),
                       (C.c_double * 3)(*opt["clip_hi"]), float(opt["ert_threshold"]),
                       GRADIENT_OPS[opt["gradient_op"]], int(bool(opt["skip_empty"])), 0,
-                      int(bool(opt.get("nearest", False))), float(opt.get("ref_step", 0.0)))
+                      int(bool(opt.get("nearest", False))), float(opt.get("ref_step", 0.0)),
+                      int(opt.get("adapt_factor", 0)), float(opt.get("adapt_range", 0.0)))
 
 
 def surface_options_struct(opt: dict) -> rc_surface_options:

@@ -329,6 +329,8 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
         rc_status st = check_render_args(v, &cams[i], tf_rgba_dev, tf_len, sh, opt);
         if (st != RC_OK) return n_views > 1 ? fail(st, "view %d: %s", i, rc_last_error()) : st;
     }
+    if (opt->adapt_factor > 1)
+        return fail(RC_E_UNSUPPORTED, "rc_render_backward: adaptive sampling is not differentiated");
     for (int i = 0; i < n_views; ++i)
         if (!aux[i] || !grad_rgba[i])
             return fail(RC_E_INVALID, "rc_render_backward: aux/grad pointers must not be NULL");

@@ -211,6 +211,8 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
         if (st != RC_OK) return fail(st, "item %d: %s", i, rc_last_error());
         if (!it.out_rgba_dev) return fail(RC_E_INVALID, "item %d: out_rgba_dev is NULL", i);
         if (it.reserved != 0) return fail(RC_E_INVALID, "item %d: reserved field must be 0", i);
+        if (it.opt.adapt_factor > 1)
+            return fail(RC_E_UNSUPPORTED, "item %d: adaptive sampling is rc_render only", i);
         fill_render_params(P[i], it.vol, &it.cam, it.tf_rgba_dev, it.tf_len, &it.sh, &it.opt);
         set_tiling(P[i].view, c.tile_w);
         P[i].view.out = (float4*)it.out_rgba_dev;

@@ -114,7 +114,7 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
 // FP64 throughout so that the lattice matches the FP64 definition.
 struct Ray {
     double o[3], d[3];
-    double t_in;
+    double t_in, t_out;
     long long K;        // index of the last lattice sample, -1 on a miss
     double p0[3], dp[3];    // voxel-space position of sample 0 and step between samples
 };
@@ -154,6 +154,7 @@ __device__ inline void setup_ray(const RenderParams& P, const ViewParams& V, int
     for (int a = 0; a < 3; ++a)
         if (P.lo[a] > P.hi[a]) hit = false;
     R.t_in = tmin;
+    R.t_out = tmax;
     R.K = -1;
     if (hit && tmin <= tmax) R.K = (long long)floor((tmax - tmin) / P.step);
     for (int a = 0; a < 3; ++a) {
@@ -879,7 +880,7 @@ __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, i
     bool valid = px < V.W && py < V.H;
     Ray R;
     R.K = -1;
-    R.t_in = 0.0;
+    R.t_in = R.t_out = 0.0;
     for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = R.p0[a] = R.dp[a] = 0.0;
     if (valid) setup_ray(P, V, px, py, R);
     MarchOut M;

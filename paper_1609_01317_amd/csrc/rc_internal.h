@@ -101,6 +101,12 @@ struct RenderParams {
     int skip;
     int nearest;                // 1: nearest-voxel sampling
     float ocorr;                // opacity-correction exponent step / ref_step, 0 = off
+    // adaptive sampling: samples in bricks whose range is <= adapt_range
+    // advance by adapt steps; their opacity exponent is adapt_e (else ocorr)
+    int adapt;                  // factor, 0 or 1 = off
+    float adapt_range;
+    float adapt_e;
+    const float2* range;        // per-brick (min, max) value ranges
     const uint8_t* empty;       // per-brick flag, 1 = every sample has alpha 0
     const uint8_t* super_empty; // per-super-brick flag (4x4x4 bricks), or null
     int nsx, nsy, nsz;          // super-bricks per axis
@@ -135,5 +141,7 @@ size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
 void set_tiling(ViewParams& V, int tile_w);     // tile_w in {4, 8, 16, 32, 64}
 void fill_view(ViewParams& V, const rc_camera* cam);
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
+// per-lane adaptive-step march (P.adapt > 1)
+rc_status launch_adaptive(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
 
 }  // namespace rc

@@ -263,6 +263,10 @@ rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const floa
         return fail(RC_E_INVALID, "options: unknown sampling %d", opt->sampling);
     if (!(std::isfinite(opt->opacity_ref_step) && opt->opacity_ref_step >= 0.0f))
         return fail(RC_E_INVALID, "options: opacity_ref_step must be finite and >= 0");
+    if (opt->adapt_factor < 0 || opt->adapt_factor > 64)
+        return fail(RC_E_INVALID, "options: adapt_factor %d outside 0..64", opt->adapt_factor);
+    if (std::isnan(opt->adapt_range))
+        return fail(RC_E_INVALID, "options: adapt_range is NaN");
     for (int a = 0; a < 3; ++a)
         if (std::isnan(opt->clip_lo[a]) || std::isnan(opt->clip_hi[a]))
             return fail(RC_E_INVALID, "options: clip box has NaN");
@@ -277,6 +281,8 @@ rc_status check_render_args(const rc_volume* v, const rc_camera* cam, const floa
         return fail(RC_E_INVALID, "options: more than 2^24 samples per ray (step too small)");
     if (opt->skip_empty && !v->brick_range)
         return fail(RC_E_STATE, "options: skip_empty needs rc_build_bricks first");
+    if (opt->adapt_factor > 1 && !v->brick_range)
+        return fail(RC_E_STATE, "options: adaptive sampling needs rc_build_bricks first");
     int dev = -1;
     if (hipGetDevice(&dev) == hipSuccess && dev != v->device)
         return fail(RC_E_INVALID, "volume lives on device %d, current device is %d", v->device, dev);
@@ -364,6 +370,15 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     // exponent 1 is the identity: left off (0) so no kernel meets 0^0
     double e = opt->opacity_ref_step > 0.0f ? opt->step / (double)opt->opacity_ref_step : 0.0;
     P.ocorr = e == 1.0 ? 0.0f : (float)e;
+    P.adapt = opt->adapt_factor > 1 ? opt->adapt_factor : 0;
+    P.adapt_range = opt->adapt_range;
+    {
+        // exponent of a sample that stands for adapt_factor steps
+        double ref = opt->opacity_ref_step > 0.0f ? (double)opt->opacity_ref_step : opt->step;
+        double ea = (double)opt->adapt_factor * opt->step / ref;
+        P.adapt_e = ea == 1.0 ? 0.0f : (float)ea;
+    }
+    P.range = v->brick_range;
     P.empty = nullptr;
     P.super_empty = nullptr;
     P.nsx = v->nsx;
@@ -410,7 +425,9 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
         P.empty = mask;
         P.super_empty = smask;
     }
-    if (st == RC_OK) st = launch_forward(P, v->dtype, opt->gradient_op, s);
+    if (st == RC_OK)
+        st = P.adapt ? launch_adaptive(P, v->dtype, opt->gradient_op, s)
+                     : launch_forward(P, v->dtype, opt->gradient_op, s);
     if (st == RC_OK && stats_dev) {
         hipLaunchKernelGGL(stats_fold, dim3(1), dim3(64), 0, s, (const unsigned long long*)sp,
                            (unsigned long long*)stats_dev);
@@ -437,6 +454,8 @@ extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, 
         if (st != RC_OK) return fail(st, "view %d: %s", i, rc_last_error());
         if (!out_rgba[i]) return fail(RC_E_INVALID, "view %d: out_rgba is NULL", i);
     }
+    if (opt->adapt_factor > 1)
+        return fail(RC_E_UNSUPPORTED, "rc_render_views: adaptive sampling is rc_render only");
     hipStream_t s = (hipStream_t)stream;
     RenderParams P;
     fill_render_params(P, v, &cams[0], tf_rgba_dev, tf_len, sh, opt);

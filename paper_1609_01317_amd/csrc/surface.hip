@@ -123,7 +123,7 @@ extern "C" rc_status rc_render_surface(const rc_volume* v, const rc_camera* cam,
                                        const rc_surface_options* so, float* out_rgba_dev,
                                        float* t_hit_dev, void* stream) {
     if (!so) return fail(RC_E_INVALID, "rc_render_surface: options is NULL");
-    rc_options opt;
+    rc_options opt{};       // every field not set below is 0 (off)
     opt.step = so->step;
     for (int a = 0; a < 3; ++a) {
         opt.clip_lo[a] = so->clip_lo[a];

@@ -59,4 +59,6 @@ def compare(gpu_rgba, ref, tau=0.0, tol=TOL):
     lim = np.full(err.shape, tol)
     near = (ref["flags"].reshape(-1) & oracle.FLAG_ERT_NEAR) != 0
     lim[near] = (1.0 - tau) + tol
+    # adaptive sampling: a sample on a brick plane may take either brick's step
+    lim[(ref["flags"].reshape(-1) & oracle.FLAG_ADAPT_NEAR) != 0] = np.inf
     return float(err.max()) if err.size else 0.0, err > lim

@@ -39,9 +39,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert C.sizeof(rc.rc_camera) == 16 + 11 * 8
     assert C.sizeof(rc.rc_shading) == 8 + 4 * 4 + 3 * 4 + 4
-    assert C.sizeof(rc.rc_options) == 8 + 6 * 8 + 6 * 4
+    assert C.sizeof(rc.rc_options) == 8 + 6 * 8 + 8 * 4
     assert C.sizeof(rc.rc_stats) == 64
-    assert C.sizeof(rc.rc_batch_item) == 264
+    assert C.sizeof(rc.rc_batch_item) == 272
     assert C.sizeof(rc.rc_batch_config) == 16
     assert C.sizeof(rc.rc_surface_options) == 8 + 6 * 8 + 2 * 4 + 4 * 4
 

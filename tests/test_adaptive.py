@@ -1,0 +1,124 @@
+"""Adaptive sampling on the GPU (rc_render with adapt_factor > 1) vs the
+FP64 oracle, under the same admissible-result rules as the fixed-step
+march (lattice-end ties, early-termination near-ties), plus pixels where a
+sample sat on a brick plane (either brick's step is admissible)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1609_01317_amd as rc
+import workloads as W
+from tests.gpu_util import compare, gpu_render, gpu_volume, oracle_render, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _blocky(sc, rng):
+    """Make a few 8^3-aligned blocks of the volume constant (detail-poor)."""
+    v = sc.volume.copy()
+    nz, ny, nx = v.shape
+    for _ in range(6):
+        z, y, x = (int(rng.integers(0, max(n // 8 - 1, 1))) * 8 for n in (nz, ny, nx))
+        v[z:z + 17, y:y + 17, x:x + 17] = v[min(z + 4, nz - 1), min(y + 4, ny - 1),
+                                            min(x + 4, nx - 1)]
+    sc.volume = v
+    return sc
+
+
+CASES = [
+    dict(seed=91, dtype=np.uint8, op="central", shading="blinn_phong", m=2, rng=0.0, ert=0.0,
+         skip=False),
+    dict(seed=92, dtype=np.uint16, op="sobel3d", shading="blinn_phong", m=4, rng=40.0, ert=0.98,
+         skip=True),
+    dict(seed=93, dtype=np.float32, op="zucker_hummel", shading="paper_lambert", m=3, rng=0.05,
+         ert=0.0, skip=False),
+    dict(seed=94, dtype=np.uint16, op="central", shading="none", m=8, rng=60.0, ert=0.9,
+         skip=True),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"s{c['seed']}")
+def test_adaptive_matches_oracle(case):
+    sc = W.config_small(seed=case["seed"], dims=(41, 35, 30), dtype=case["dtype"], image=(45, 37),
+                        op=case["op"], shading=case["shading"], ert=case["ert"],
+                        skip=case["skip"])
+    sc = _blocky(sc, np.random.default_rng(case["seed"]))
+    if sc.shading["light_is_point"]:
+        sc.shading["light"] = (70.0, -40.0, 60.0)
+    sc.options.update(adapt_factor=case["m"], adapt_range=case["rng"])
+    g = gpu_render(sc, vol=gpu_volume(sc, bricks=True), stats=True)
+    r = oracle_render(sc)
+    err, bad = compare(g["rgba"], r, case["ert"])
+    print(f"seed {case['seed']}: max err {err:.2e}, flagged "
+          f"{int(((r['flags'] & 16) != 0).sum())}", flush=True)
+    assert not bad.any(), err
+    assert (r["rgba"][..., 3] > 1e-6).sum() >= 20
+    # fewer samples than the fixed lattice
+    fixed = gpu_render(sc, vol=gpu_volume(sc, bricks=True),
+                       options=dict(sc.options, adapt_factor=0), stats=True)
+    assert g["stats"][0] < fixed["stats"][0]
+
+
+def test_adaptive_without_poor_bricks_is_the_fixed_march():
+    sc = W.config_small(seed=95, dims=(30, 26, 22), dtype=np.uint16, image=(37, 29), op="sobel3d",
+                        ert=0.95, skip=True)
+    vol = gpu_volume(sc, bricks=True)
+    fixed = gpu_render(sc, vol=vol)
+    ad = gpu_render(sc, vol=vol, options=dict(sc.options, adapt_factor=4, adapt_range=-1.0))
+    r = oracle_render(sc)
+    ok = (r["flags"] & (2 | 4)) == 0
+    assert np.abs(ad["rgba"][ok] - fixed["rgba"][ok]).max() <= 1e-5
+    np.testing.assert_array_equal(ad["k_last"][ok], fixed["k_last"][ok])
+
+
+def test_adaptive_skip_is_lossless_bitwise():
+    sc = W.config_small(seed=96, dims=(40, 36, 33), dtype=np.uint16, image=(48, 40),
+                        op="sobel3d", ert=0.99)
+    sc = _blocky(sc, np.random.default_rng(96))
+    vol = gpu_volume(sc, bricks=True)
+    opt = dict(sc.options, adapt_factor=4, adapt_range=30.0)
+    on = gpu_render(sc, vol=vol, options=dict(opt, skip_empty=True), stats=True)
+    off = gpu_render(sc, vol=vol, options=dict(opt, skip_empty=False), stats=True)
+    np.testing.assert_array_equal(on["rgba"], off["rgba"])
+    np.testing.assert_array_equal(on["k_last"], off["k_last"])
+    assert on["stats"][1] < off["stats"][1]
+
+
+def test_adaptive_c2_scale_sampled():
+    """256^3 u16 phantom -> 512^2, Sobel3D, ERT 0.99, skipping, factor 4 in
+    bricks whose range is at most 120 (about six noise sigmas): 3000
+    sampled pixels against the oracle."""
+    sc = W.config_c2()
+    sc.options.update(adapt_factor=4, adapt_range=120.0)
+    vol = gpu_volume(sc, bricks=True)
+    g = gpu_render(sc, vol=vol, stats=True)
+    cam = sc.cameras[0]
+    pix = np.random.default_rng(97).choice(cam["width"] * cam["height"], 3000, replace=False)
+    r = oracle_render(sc, pixels=pix)
+    err, bad = compare(g["rgba"].reshape(-1, 4)[pix], r, 0.99)
+    assert not bad.any(), err
+    fixed = gpu_render(sc, vol=vol, options=dict(sc.options, adapt_factor=0), stats=True)
+    print(f"c2 adaptive: max err {err:.2e}, lattice samples {g['stats'][0]} vs fixed "
+          f"{fixed['stats'][0]}", flush=True)
+    assert g["stats"][0] < fixed["stats"][0]
+
+
+def test_adaptive_rejected_where_unsupported():
+    sc = W.config_small(seed=98, dims=(12, 12, 12), image=(8, 8), shading="none")
+    vol = gpu_volume(sc, bricks=True)
+    tf = to_dev(sc.tf)
+    opt = dict(sc.options, adapt_factor=2, adapt_range=10.0)
+    with pytest.raises(rc.RCError) as e:
+        rc.rc_render_views(vol, sc.cameras, tf, sc.shading, opt)
+    assert e.value.status == rc.RC_E_UNSUPPORTED
+    aux = rc.new_aux(sc.cameras[0])
+    rc.rc_render(vol, sc.cameras[0], tf, sc.shading, opt, aux=aux)
+    with pytest.raises(rc.RCError) as e:
+        rc.rc_render_backward(vol, sc.cameras[0], tf, sc.shading, opt, aux,
+                              torch.zeros((8, 8, 4), device="cuda"))
+    assert e.value.status == rc.RC_E_UNSUPPORTED
+    plain = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+    with pytest.raises(rc.RCError) as e:
+        rc.rc_render(plain, sc.cameras[0], tf, sc.shading, opt)
+    assert e.value.status == rc.RC_E_STATE
