@@ -204,6 +204,37 @@ def test_degenerate_volumes_and_short_tables():
     _check(sc)
 
 
+def test_maximum_extents():
+    """The edges of the accepted sizes: a 4096-voxel volume axis (the largest
+    edge) marched end to end, a 16384-pixel-wide image (the largest image
+    edge), and a 65536-entry table; against the oracle (sampled pixels for
+    the wide image)."""
+    sc = W.config_small(seed=30, dims=(4096, 9, 10), dtype=np.uint8, image=(4, 4),
+                        op="sobel3d", ert=0.0, skip=True)
+    sc.volume = W.blob_volume((10, 9, 4096), 300, seed=30, dtype=np.uint8, sigma=(2.0, 5.0),
+                              centre_lo=0.0, centre_hi=1.0)
+    sc.tf = W.tf_ramps(65536, seed=31, alpha_min=0.002, alpha_max=0.01, lo=0.08, hi=0.9)
+    # rays along the long axis: about 8190 samples each
+    along = {"projection": "ortho", "eye": (-50.0, 4.0, 4.5), "target": (0.0, 4.0, 4.5),
+             "up": (0.0, 0.0, 1.0), "fov_y_deg": 60.0, "ortho_height": 7.0, "width": 5,
+             "height": 4}
+    g = gpu_render(sc, cam=along)
+    r = oracle_render(sc, cam=along)
+    err, bad = compare(g["rgba"], r, 0.0)
+    assert not bad.any(), err
+    assert r["k_last"].max() > 8000 and (r["rgba"][..., 3] > 1e-6).sum() >= 10
+    # a 16384 x 2 image across the long axis
+    across = {"projection": "ortho", "eye": (2047.5, -60.0, 4.5), "target": (2047.5, 0.0, 4.5),
+              "up": (0.0, 0.0, 1.0), "fov_y_deg": 60.0, "ortho_height": 2.5, "width": 16384,
+              "height": 2}
+    g = gpu_render(sc, cam=across)
+    pix = np.random.default_rng(30).choice(16384 * 2, 2000, replace=False)
+    r = oracle_render(sc, cam=across, pixels=pix)
+    err, bad = compare(g["rgba"].reshape(-1, 4)[pix], r, 0.0)
+    assert not bad.any(), err
+    assert (r["rgba"][:, 3] > 1e-6).sum() >= 100
+
+
 def test_empty_clip_box_gives_black():
     sc = W.config_small(seed=19, dims=(12, 12, 12), image=(16, 16))
     opt = dict(sc.options, clip_lo=(8.0, 0.0, 0.0), clip_hi=(4.0, 20.0, 20.0))
