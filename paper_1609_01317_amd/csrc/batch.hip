@@ -113,8 +113,9 @@ __global__ __launch_bounds__(256) void batch_super(const MaskJob* __restrict__ j
     super_all[g] = all;
 }
 
-// The persistent kernel.  `kind` = dtype * 3 + gradient operator selects the
-// instantiation per work unit (uniform across the wave).
+// The persistent kernel.  `kind` selects the instantiation per work unit
+// (uniform across the wave): dtype * 3 + gradient operator for shaded items,
+// 9 + dtype for unshaded ones.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void raycast_batch(const RenderParams* __restrict__ items,
                                                      const int* __restrict__ kinds,
                                                      const int* __restrict__ tile_off,
@@ -137,15 +138,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
         int tile = w - tile_off[lo];
         const RenderParams& P = items[item];
         switch (kinds[item]) {
-            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL>(P, P.view, tile, lane, (uint8_t*)lds); break;
-            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D>(P, P.view, tile, lane, (uint8_t*)lds); break;
-            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL>(P, P.view, tile, lane, (uint8_t*)lds); break;
-            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL>(P, P.view, tile, lane, (uint16_t*)lds); break;
-            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D>(P, P.view, tile, lane, (uint16_t*)lds); break;
-            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL>(P, P.view, tile, lane, (uint16_t*)lds); break;
-            case 6: render_tile<float, RC_GRAD_CENTRAL>(P, P.view, tile, lane, (float*)lds); break;
-            case 7: render_tile<float, RC_GRAD_SOBEL3D>(P, P.view, tile, lane, (float*)lds); break;
-            default: render_tile<float, RC_GRAD_ZUCKER_HUMMEL>(P, P.view, tile, lane, (float*)lds); break;
+            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, (uint8_t*)lds); break;
+            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, (uint8_t*)lds); break;
+            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, (uint8_t*)lds); break;
+            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, (uint16_t*)lds); break;
+            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, (uint16_t*)lds); break;
+            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, (uint16_t*)lds); break;
+            case 6: render_tile<float, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, (float*)lds); break;
+            case 7: render_tile<float, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, (float*)lds); break;
+            case 8: render_tile<float, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, (float*)lds); break;
+            // unshaded items: no gradient, one instantiation per voxel type
+            case 9: render_tile<uint8_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, (uint8_t*)lds); break;
+            case 10: render_tile<uint16_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, (uint16_t*)lds); break;
+            default: render_tile<float, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, (float*)lds); break;
         }
     }
 }
@@ -217,7 +222,8 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
         set_tiling(P[i].view, c.tile_w);
         P[i].view.out = (float4*)it.out_rgba_dev;
         P[i].view.aux = it.aux_dev;
-        kinds[i] = (int)it.vol->dtype * 3 + it.opt.gradient_op;
+        kinds[i] = it.sh.model == RC_SHADE_NONE ? 9 + (int)it.vol->dtype
+                                                : (int)it.vol->dtype * 3 + it.opt.gradient_op;
         tiles[i] = P[i].view.n_tiles;
         if (it.opt.skip_empty) {
             MaskJob J;

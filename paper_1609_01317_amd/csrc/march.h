@@ -571,7 +571,9 @@ struct Chunk {
 
 // One evaluated sample: value, table, and for non-zero opacity the
 // gradient, shading and compositing.  Returns true when the ray terminates.
-template <typename VT, int OP, typename Src>
+// LIT: a shading model is on (the unshaded instantiations carry none of the
+// gradient's registers, so they keep more waves resident).
+template <typename VT, int OP, bool LIT, typename Src>
 __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& src, const Cell& C,
                                              const double pv[3], const RayShade& rs,
                                              LaneState& S) {
@@ -585,7 +587,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     if (P.ocorr > 0.0f) a = correct_opacity(P, a);
     ++S.shaded;
     float c[3] = {rgba.x, rgba.y, rgba.z};
-    if (P.shade != RC_SHADE_NONE) {
+    if (LIT) {
         float g[3];
         gradient<VT, OP, true>(P, src.base, ox, oy, oz, C, g, corner);
         shade(P, rgba, g, pv, rs, c);
@@ -602,7 +604,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
 // bricks known to be empty are not evaluated (their opacity is exactly 0,
 // so they change nothing).  A sample reads the LDS box when `staged` and its
 // 4x4x4 footprint lies inside the box, else the bricked volume.
-template <typename VT, int OP>
+template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
                                             const LdsSrc<VT>& lsrc, const GlobalSrc<VT>& gsrc,
                                             bool staged, const Chunk& ch, long long kstop,
@@ -630,8 +632,8 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
         // a staged chunk's samples always read the box.
         const bool in = staged;
         S.direct += in ? 0u : 1u;
-        bool term = in ? shade_sample<VT, OP>(P, lsrc, C, pv, rs, S)
-                       : shade_sample<VT, OP>(P, gsrc, C, pv, rs, S);
+        bool term = in ? shade_sample<VT, OP, LIT>(P, lsrc, C, pv, rs, S)
+                       : shade_sample<VT, OP, LIT>(P, gsrc, C, pv, rs, S);
         if (term) {
             S.k_term = k;
             S.done = true;
@@ -747,8 +749,9 @@ __device__ __forceinline__ long long entry_index(const RenderParams& P, const Ra
 }
 
 // March the 64 rays of this wave together.  `has_ray` is false for lanes
-// outside the image; they still take part in the wave-wide steps.
-template <typename VT, int OP>
+// outside the image; they still take part in the wave-wide steps.  LIT must
+// equal (P.shade != RC_SHADE_NONE).
+template <typename VT, int OP, bool LIT>
 __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_ray, VT* lds,
                                   int lane, MarchOut& M) {
     LaneState S;
@@ -763,7 +766,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     unsigned n_staged = 0, n_empty = 0, n_direct = 0;
     // Staging pays off when samples need the stencil neighbourhood; an
     // unshaded march reads 8 voxels per sample and gathers them directly.
-    const bool stage = P.shade != RC_SHADE_NONE;
+    const bool stage = LIT;
     RayShade rs;
     ray_shade(P, R, rs);
     const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
@@ -852,7 +855,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
         }
         LdsSrc<VT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1]};
         if (active && kstop >= S.k)
-            run_samples<VT, OP>(P, R, lsrc, gsrc, fits, ch, kstop, rs, S);
+            run_samples<VT, OP, LIT>(P, R, lsrc, gsrc, fits, ch, kstop, rs, S);
         if (fits) wave_lds_sync();
         if (active && !S.done && kstop >= S.k) S.k = kstop + 1;
     }
@@ -871,7 +874,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
 // One wave renders one tile of tile_w x (64 / tile_w) pixels; `tile` is the
 // tile's row-major index in the image.  Lanes outside the image take part
 // in the wave-wide steps without a ray.
-template <typename VT, int OP>
+template <typename VT, int OP, bool LIT>
 __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, int tile, int lane,
                                    VT* lds) {
     const int tw = V.tile_w, th = 64 / V.tile_w;
@@ -884,7 +887,7 @@ __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, i
     for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = R.p0[a] = R.dp[a] = 0.0;
     if (valid) setup_ray(P, V, px, py, R);
     MarchOut M;
-    march_wave<VT, OP>(P, R, valid, lds, lane, M);
+    march_wave<VT, OP, LIT>(P, R, valid, lds, lane, M);
     if (valid) {
         long long pix = (long long)py * V.W + px;
         V.out[pix] = M.rgba;

@@ -95,28 +95,32 @@ size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
 
 // ---------------------------------------------------------------- the kernel
 // Workgroup = one wave = one pixel tile, placed by tile_of_block.
-// Three resident waves per SIMD: the register allocator keeps the march
-// within 168 VGPRs.
-template <typename VT, int OP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void raycast_fwd(
-    RenderParams P) {
-    __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
+// Shaded renders keep three waves per SIMD (the register allocator holds
+// the march within 168 VGPRs); unshaded ones need neither the gradient's
+// registers nor the LDS box and ask for eight.
+constexpr int waves_for(bool lit) { return lit ? 3 : 6; }
+constexpr int lds_for(bool lit) { return lit ? kWaveLdsBytes : 16; }
+
+template <typename VT, int OP, bool LIT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(LIT)))) void
+raycast_fwd(RenderParams P) {
+    __shared__ __align__(16) unsigned char lds[lds_for(LIT)];
     const ViewParams& V = P.view;
     int tile = tile_of_block(blockIdx.x, V.tiles_x, V.n_tiles / V.tiles_x);
-    if (tile >= 0) render_tile<VT, OP>(P, V, tile, threadIdx.x, (VT*)lds);
+    if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, (VT*)lds);
 }
 
 // Several views of one volume: each view owns a run of blocks (a multiple of
 // the XCD group size, so the group dealing above holds inside every view).
-template <typename VT, int OP>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void raycast_views(
-    RenderParams P, ViewSet S) {
-    __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
+template <typename VT, int OP, bool LIT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(LIT)))) void
+raycast_views(RenderParams P, ViewSet S) {
+    __shared__ __align__(16) unsigned char lds[lds_for(LIT)];
     int b = blockIdx.x, v = 0;
     while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
     const ViewParams& V = S.v[v];
     int tile = tile_of_block(b - S.block_off[v], V.tiles_x, V.n_tiles / V.tiles_x);
-    if (tile >= 0) render_tile<VT, OP>(P, V, tile, threadIdx.x, (VT*)lds);
+    if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, (VT*)lds);
 }
 
 // ---------------------------------------------------------------- counters
@@ -141,12 +145,14 @@ template <typename VT>
 static void launch_fwd_t(const RenderParams& P, int op, hipStream_t st) {
     const ViewParams& V = P.view;
     dim3 grid((unsigned)group_grid_blocks(V.tiles_x, V.n_tiles / V.tiles_x)), block(64);
-    if (op == RC_GRAD_CENTRAL)
-        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_CENTRAL>), grid, block, 0, st, P);
+    if (P.shade == RC_SHADE_NONE)           // no gradient: the operator does not matter
+        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_CENTRAL, false>), grid, block, 0, st, P);
+    else if (op == RC_GRAD_CENTRAL)
+        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_CENTRAL, true>), grid, block, 0, st, P);
     else if (op == RC_GRAD_SOBEL3D)
-        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_SOBEL3D>), grid, block, 0, st, P);
+        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_SOBEL3D, true>), grid, block, 0, st, P);
     else
-        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_ZUCKER_HUMMEL>), grid, block, 0, st, P);
+        hipLaunchKernelGGL((raycast_fwd<VT, RC_GRAD_ZUCKER_HUMMEL, true>), grid, block, 0, st, P);
 }
 
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st) {
@@ -160,12 +166,15 @@ rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t
 template <typename VT>
 static void launch_views_t(const RenderParams& P, const ViewSet& S, int op, hipStream_t st) {
     dim3 grid((unsigned)S.block_off[S.n]), block(64);
-    if (op == RC_GRAD_CENTRAL)
-        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_CENTRAL>), grid, block, 0, st, P, S);
+    if (P.shade == RC_SHADE_NONE)
+        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_CENTRAL, false>), grid, block, 0, st, P, S);
+    else if (op == RC_GRAD_CENTRAL)
+        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_CENTRAL, true>), grid, block, 0, st, P, S);
     else if (op == RC_GRAD_SOBEL3D)
-        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_SOBEL3D>), grid, block, 0, st, P, S);
+        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_SOBEL3D, true>), grid, block, 0, st, P, S);
     else
-        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_ZUCKER_HUMMEL>), grid, block, 0, st, P, S);
+        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_ZUCKER_HUMMEL, true>), grid, block, 0, st, P,
+                           S);
 }
 
 static rc_status launch_views(const RenderParams& P, const ViewSet& S, rc_dtype dt, int op,
