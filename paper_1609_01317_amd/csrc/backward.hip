@@ -45,14 +45,23 @@ struct BwdSample {
     float c[3];                 // colour
 };
 
-template <typename VT, int OP, bool LIT>
-__device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R,
-                                           const RayShade& rs, long long k, bool lit,
-                                           BwdSample& S) {
+// Sample k's position, footprint offsets and its cell's 8 voxels (the loads
+// are issued here and consumed by bwd_finish, so a caller can overlap them
+// with other work).
+template <typename VT>
+__device__ __forceinline__ void bwd_fetch(const RenderParams& P, const Ray& R, long long k,
+                                          BwdSample& S, float corner[8]) {
     lattice_point(P, R, k, S.C, S.pv);
     const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
     src.offsets(S.C, S.ox, S.oy, S.oz);
-    float v = sample_value<VT>(src.base, S.ox, S.oy, S.oz, S.C);
+    load_corners<VT>(src.base, S.ox, S.oy, S.oz, corner);
+}
+
+template <typename VT, int OP, bool LIT>
+__device__ __forceinline__ void bwd_finish(const RenderParams& P, const RayShade& rs, bool lit,
+                                           const float corner[8], BwdSample& S) {
+    const VT* base = (const VT*)P.vox;
+    float v = trilinear(corner, S.C);
     S.vn = (v - P.vmin) * P.inv_range;
     float uu = fminf(fmaxf(S.vn, 0.0f), 1.0f) * P.Mm1;
     S.i = min((int)uu, P.M - 1);
@@ -75,9 +84,18 @@ __device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R,
     }
     S.c[0] = S.rgba.x; S.c[1] = S.rgba.y; S.c[2] = S.rgba.z;
     if (LIT && lit) {
-        gradient<VT, OP>(P, src.base, S.ox, S.oy, S.oz, S.C, S.g);
+        gradient<VT, OP, true>(P, base, S.ox, S.oy, S.oz, S.C, S.g, corner);
         shade(P, S.rgba, S.g, S.pv, rs, S.c);
     }
+}
+
+template <typename VT, int OP, bool LIT>
+__device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R,
+                                           const RayShade& rs, long long k, bool lit,
+                                           BwdSample& S) {
+    float corner[8];
+    bwd_fetch<VT>(P, R, k, S, corner);
+    bwd_finish<VT, OP, LIT>(P, rs, lit, corner, S);
 }
 
 // Reverse of shade(): dL/dc -> dL/d(table rgb) and dL/dG, through the same
@@ -231,7 +249,8 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
 // runs of workgroups (ViewSet::block_off).  LIT: a shading model is on (the
 // unshaded kernel carries none of the lighting and stencil registers).
 template <typename VT, int OP, bool LIT>
-__global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 1 : 5))) void
+raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
     extern __shared__ float lds[];
     if (Bp.lds_tf) {
         for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) lds[i] = 0.0f;
@@ -276,9 +295,15 @@ __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, Ba
             float Bk1[3] = {0.f, 0.f, 0.f};
             float Pk1 = 1.0f;       // prod over samples behind k of (1 - a)
             float Q = 1.0f;         // prod over samples k .. anchor-1 of (1 - a)
+            // unshaded: one sample ahead, the voxels of sample k-1 are in
+            // flight while sample k is accumulated (the shaded path re-reads
+            // 64 voxels per sample and keeps no second sample in registers)
+            BwdSample S, Sn;
+            float corner[8], cn[8];
+            bwd_fetch<VT>(P, R, last, S, corner);
+            bwd_finish<VT, OP, LIT>(P, rs, true, corner, S);
             for (long long k = last; k >= 0; --k) {
-                BwdSample S;
-                bwd_sample<VT, OP, LIT>(P, R, rs, k, true, S);
+                if (!LIT && k > 0) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
                 float om = 1.0f - S.a;
                 if (k < anchor) {
                     Q *= om;
@@ -289,6 +314,11 @@ __global__ __launch_bounds__(256) void raycast_bwd(RenderParams P, ViewSet S, Ba
                 Bk1[1] = fmaf(S.a, S.c[1], om * Bk1[1]);
                 Bk1[2] = fmaf(S.a, S.c[2], om * Bk1[2]);
                 Pk1 *= om;
+                if (k > 0) {
+                    if (LIT) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
+                    bwd_finish<VT, OP, LIT>(P, rs, true, cn, Sn);
+                    S = Sn;
+                }
             }
         }
     }

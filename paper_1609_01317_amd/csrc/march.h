@@ -246,12 +246,16 @@ struct LdsSrc {
 // ---------------------------------------------------------------- sampling
 // Trilinear interpolation as 7 lerps, x then y then z (Section 3.4, eq. 2).
 template <typename VT>
-__device__ __forceinline__ float sample_value(const VT* base, const int ox[4], const int oy[4],
-                                              const int oz[4], const Cell& C, float corner[8]) {
+__device__ __forceinline__ void load_corners(const VT* base, const int ox[4], const int oy[4],
+                                             const int oz[4], float corner[8]) {
     // corner[(z-1)*4 + (y-1)*2 + (x-1)] = voxel (x, y, z) of the 4x4x4 footprint
 #pragma unroll
     for (int q = 0; q < 8; ++q)
         corner[q] = (float)base[ox[1 + (q & 1)] + oy[1 + ((q >> 1) & 1)] + oz[1 + (q >> 2)]];
+}
+
+// Section 3.4: 7 lerps, x then y then z, of the cell's 8 voxels.
+__device__ __forceinline__ float trilinear(const float corner[8], const Cell& C) {
     const float v000 = corner[0], v100 = corner[1], v010 = corner[2], v110 = corner[3];
     const float v001 = corner[4], v101 = corner[5], v011 = corner[6], v111 = corner[7];
     float i1 = lerpf(v000, v100, C.fr[0]);
@@ -261,6 +265,13 @@ __device__ __forceinline__ float sample_value(const VT* base, const int ox[4], c
     float i5 = lerpf(i1, i2, C.fr[1]);
     float i6 = lerpf(i3, i4, C.fr[1]);
     return lerpf(i5, i6, C.fr[2]);
+}
+
+template <typename VT>
+__device__ __forceinline__ float sample_value(const VT* base, const int ox[4], const int oy[4],
+                                              const int oz[4], const Cell& C, float corner[8]) {
+    load_corners<VT>(base, ox, oy, oz, corner);
+    return trilinear(corner, C);
 }
 
 template <typename VT>
