@@ -749,13 +749,13 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
 /* coarse forward march finds the first sample inside the window, then   */
 /* hitpoint refinement halves the step again and again, moving back from */
 /* a sample inside the window and forward from one outside it.           */
-/* Reading: "closer to the target value" is taken as "on the window side */
-/* of the boundary"; the refinement is then a bisection of the last      */
-/* coarse interval, 2^n times finer after n steps (the "64 times" that   */
-/* Section 5.1 quotes for 6 steps).  A ray whose first sample is already */
-/* inside (a clip plane through the object) is not refined.  The refined */
-/* point is shaded with the gradient there and coloured by the TF's rgb  */
-/* at its value.                                                         */
+/* Reading: getting closer to the target value is taken as being on the  */
+/* window side of the boundary; the refinement is then a bisection of    */
+/* the last coarse interval, 2^n times finer after n steps (the 64-fold  */
+/* gain Section 5.1 credits to 6 steps).  A ray whose first sample is    */
+/* already inside (a clip plane through the object) is not refined.  The */
+/* refined point is shaded with the gradient there and coloured by the  */
+/* TF's rgb at its value.                                                */
 /* ------------------------------------------------------------------ */
 static int in_window(double val, const orc_surface_options* o) {
     return val >= o->iso_lo && val <= o->iso_hi;
