@@ -26,6 +26,44 @@ __device__ __forceinline__ void add_dtf(const BackwardParams& B, float* lds, int
     else unsafeAtomicAdd(&B.dtf[i * 4 + ch], v);
 }
 
+// A ray's table-gradient contributions, summed in registers while its
+// samples stay between the same two entries (i, i+1) and added to the
+// shared sum when the entry pair changes or the ray ends.  Neighbouring
+// samples mostly share the pair (all of a transparent background reads
+// entry 0), so this replaces most of the same-address atomics that
+// serialise when every lane of a wave adds to one entry.
+struct DtfRun {
+    int i = -1;                 // lower entry, -1 = empty
+    float a0[4], a1[4];         // contributions to entries i and min(i + 1, M - 1)
+};
+
+__device__ __forceinline__ void dtf_flush(const RenderParams& P, const BackwardParams& B, float* lds,
+                                          DtfRun& r) {
+    if (r.i < 0) return;
+    const int i1 = min(r.i + 1, P.M - 1);
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        add_dtf(B, lds, r.i, ch, r.a0[ch]);
+        add_dtf(B, lds, i1, ch, r.a1[ch]);
+    }
+    r.i = -1;
+}
+
+__device__ __forceinline__ void dtf_add(const RenderParams& P, const BackwardParams& B, float* lds,
+                                        DtfRun& r, int i, float w0, float w1, const float d[4]) {
+    if (i != r.i) {
+        dtf_flush(P, B, lds, r);
+        r.i = i;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) r.a0[ch] = r.a1[ch] = 0.0f;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        r.a0[ch] = fmaf(w0, d[ch], r.a0[ch]);
+        r.a1[ch] = fmaf(w1, d[ch], r.a1[ch]);
+    }
+}
+
 // Value, table entry pair, opacity and colour of lattice sample k.  With a
 // shading model the colour is the lit one, also where the opacity is 0:
 // the forward skips the lighting there only because the colour is
@@ -207,7 +245,8 @@ __device__ __forceinline__ void gradient_adjoint(const RenderParams& P, const Ba
 // trilinear weights; the gradient goes back through the operator's taps.
 template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const BackwardParams& Bp,
-                                               float* lds, const BwdSample& S, const RayShade& rs,
+                                               float* lds, DtfRun& run, const BwdSample& S,
+                                               const RayShade& rs,
                                                float Tk, const float4& g, const float Bk1[3],
                                                float Pk1) {
     float ta = Tk * S.a;
@@ -218,11 +257,7 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
     if (LIT && S.a != 0.0f) shade_adjoint(P, S, rs, dc, drgb, dg);
     float w0 = 1.0f - S.t, w1 = S.t;
     const float d4[4] = {drgb[0], drgb[1], drgb[2], da};
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-        add_dtf(Bp, lds, S.i, ch, w0 * d4[ch]);
-        add_dtf(Bp, lds, S.i1, ch, w1 * d4[ch]);
-    }
+    dtf_add(P, Bp, lds, run, S.i, w0, w1, d4);
     if (LIT) gradient_adjoint<OP>(P, Bp, S.C, dg);
     if (!(S.vn > 0.0f && S.vn < 1.0f)) return;      // clamped: no dependence on the value
     float du = drgb[0] * (S.e1.x - S.e0.x) + drgb[1] * (S.e1.y - S.e0.y) +
@@ -249,7 +284,7 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
 // runs of workgroups (ViewSet::block_off).  LIT: a shading model is on (the
 // unshaded kernel carries none of the lighting and stencil registers).
 template <typename VT, int OP, bool LIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 1 : 5))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 1 : 4))) void
 raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
     extern __shared__ float lds[];
     if (Bp.lds_tf) {
@@ -300,6 +335,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
             // 64 voxels per sample and keeps no second sample in registers)
             BwdSample S, Sn;
             float corner[8], cn[8];
+            DtfRun run;
             bwd_fetch<VT>(P, R, last, S, corner);
             bwd_finish<VT, OP, LIT>(P, rs, true, corner, S);
             for (long long k = last; k >= 0; --k) {
@@ -308,7 +344,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                 if (k < anchor) {
                     Q *= om;
                     float Tk = Q > 0.0f ? Ta / Q : 0.0f;
-                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, S, rs, Tk, g, Bk1, Pk1);
+                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, S, rs, Tk, g, Bk1, Pk1);
                 }
                 Bk1[0] = fmaf(S.a, S.c[0], om * Bk1[0]);
                 Bk1[1] = fmaf(S.a, S.c[1], om * Bk1[1]);
@@ -320,6 +356,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                     S = Sn;
                 }
             }
+            dtf_flush(P, Bp, lds, run);
         }
     }
     if (Bp.lds_tf) {
