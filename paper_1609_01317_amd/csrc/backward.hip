@@ -14,10 +14,12 @@ struct BackwardParams {
     float* dvol;            // [nz][ny][nx]
     float* dtf;             // [M][4]
     int lds_tf;             // 1: accumulate the table gradient in LDS first
+    int lds_table;          // 1: read the table from an LDS copy
 };
 
 constexpr int kBwdTile = 16;              // 16x16 pixels, 4 waves per workgroup
 constexpr int kBwdLdsEntries = 2048;      // table sizes up to this are privatised in LDS
+constexpr int kBwdLdsTable = 1024;        // and up to this also read from LDS
 constexpr float kTinyT = 1e-30f;
 
 __device__ __forceinline__ void add_dtf(const BackwardParams& B, float* lds, int i, int ch, float v) {
@@ -96,8 +98,9 @@ __device__ __forceinline__ void bwd_fetch(const RenderParams& P, const Ray& R, l
 }
 
 template <typename VT, int OP, bool LIT>
-__device__ __forceinline__ void bwd_finish(const RenderParams& P, const RayShade& rs, bool lit,
-                                           const float corner[8], BwdSample& S) {
+__device__ __forceinline__ void bwd_finish(const RenderParams& P, const float4* tab,
+                                           const RayShade& rs, bool lit, const float corner[8],
+                                           BwdSample& S) {
     const VT* base = (const VT*)P.vox;
     float v = trilinear(corner, S.C);
     S.vn = (v - P.vmin) * P.inv_range;
@@ -105,8 +108,8 @@ __device__ __forceinline__ void bwd_finish(const RenderParams& P, const RayShade
     S.i = min((int)uu, P.M - 1);
     S.i1 = min(S.i + 1, P.M - 1);
     S.t = uu - (float)S.i;
-    S.e0 = P.tf[S.i];
-    S.e1 = P.tf[S.i1];
+    S.e0 = tab[S.i];
+    S.e1 = tab[S.i1];
     S.rgba = make_float4(lerpf(S.e0.x, S.e1.x, S.t), lerpf(S.e0.y, S.e1.y, S.t),
                          lerpf(S.e0.z, S.e1.z, S.t), lerpf(S.e0.w, S.e1.w, S.t));
     S.a = S.rgba.w;
@@ -128,12 +131,12 @@ __device__ __forceinline__ void bwd_finish(const RenderParams& P, const RayShade
 }
 
 template <typename VT, int OP, bool LIT>
-__device__ __forceinline__ void bwd_sample(const RenderParams& P, const Ray& R,
+__device__ __forceinline__ void bwd_sample(const RenderParams& P, const float4* tab, const Ray& R,
                                            const RayShade& rs, long long k, bool lit,
                                            BwdSample& S) {
     float corner[8];
     bwd_fetch<VT>(P, R, k, S, corner);
-    bwd_finish<VT, OP, LIT>(P, rs, lit, corner, S);
+    bwd_finish<VT, OP, LIT>(P, tab, rs, lit, corner, S);
 }
 
 // Reverse of shade(): dL/dc -> dL/d(table rgb) and dL/dG, through the same
@@ -287,10 +290,15 @@ template <typename VT, int OP, bool LIT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 1 : 4))) void
 raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
     extern __shared__ float lds[];
-    if (Bp.lds_tf) {
+    const float4* tab = P.tf;
+    if (Bp.lds_tf)
         for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) lds[i] = 0.0f;
-        __syncthreads();
+    if (Bp.lds_table) {
+        float4* t = (float4*)(lds + (Bp.lds_tf ? P.M * 4 : 0));
+        for (int i = threadIdx.x; i < P.M; i += blockDim.x) t[i] = P.tf[i];
+        tab = t;
     }
+    if (Bp.lds_tf || Bp.lds_table) __syncthreads();
     int b = blockIdx.x, v = 0;
     while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
     const ViewParams& V = S.v[v];
@@ -319,7 +327,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                 anchor = 0;
                 for (long long k = 0; k <= last; ++k) {
                     BwdSample S;
-                    bwd_sample<VT, OP, LIT>(P, R, rs, k, false, S);
+                    bwd_sample<VT, OP, LIT>(P, tab, R, rs, k, false, S);
                     float Tn = T * (1.0f - S.a);
                     if (!(Tn >= kTinyT)) break;
                     T = Tn;
@@ -337,7 +345,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
             float corner[8], cn[8];
             DtfRun run;
             bwd_fetch<VT>(P, R, last, S, corner);
-            bwd_finish<VT, OP, LIT>(P, rs, true, corner, S);
+            bwd_finish<VT, OP, LIT>(P, tab, rs, true, corner, S);
             for (long long k = last; k >= 0; --k) {
                 if (!LIT && k > 0) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
                 float om = 1.0f - S.a;
@@ -352,7 +360,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                 Pk1 *= om;
                 if (k > 0) {
                     if (LIT) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
-                    bwd_finish<VT, OP, LIT>(P, rs, true, cn, Sn);
+                    bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sn);
                     S = Sn;
                 }
             }
@@ -409,7 +417,8 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
     Bp.dvol = grad_volume_dev;
     Bp.dtf = grad_tf_dev;
     Bp.lds_tf = tf_len <= kBwdLdsEntries;
-    size_t lds = Bp.lds_tf ? (size_t)tf_len * 4 * sizeof(float) : 0;
+    Bp.lds_table = tf_len <= kBwdLdsTable;
+    size_t lds = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 4 * sizeof(float);
     for (int first = 0; first < n_views; first += kMaxViews) {
         ViewSet S;
         S.n = n_views - first < kMaxViews ? n_views - first : kMaxViews;

@@ -52,6 +52,24 @@ def test_adjoint_matches_oracle_small(seed, dtype, ert, nearest, ref):
     assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
 
 
+@pytest.mark.parametrize("tf_len", [1024, 1025, 2048, 2049])
+def test_adjoint_table_sizes(tf_len):
+    """Table lengths on both sides of the two shared-memory limits of the
+    adjoint kernel: the table is read from an LDS copy up to 1024 entries and
+    its gradient summed in LDS up to 2048, in global memory beyond."""
+    sc = W.config_small(seed=38, dims=(23, 19, 17), dtype=np.float32, image=(35, 27),
+                        shading="none")
+    tf = W.tf_ramps(tf_len, seed=38, alpha_max=0.3)
+    cam = sc.cameras[0]
+    g = np.random.default_rng(38).normal(size=(cam["height"], cam["width"], 4))
+    gv, gt = _gpu_grads(sc, cam, g, tf=tf)
+    dv, dt = oracle.render_grad(oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax), cam,
+                                tf, sc.options, g)
+    print(f"M {tf_len}: rel err volume {_rel(gv, dv):.2e} tf {_rel(gt, dt):.2e}", flush=True)
+    assert np.abs(dv).max() > 0 and np.count_nonzero(dt) > 100
+    assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
+
+
 SHADED = [
     dict(seed=51, dtype=np.float32, op="central", shading="blinn_phong", nearest=False, ert=0.0),
     dict(seed=52, dtype=np.uint16, op="sobel3d", shading="blinn_phong", nearest=False, ert=0.95),
