@@ -139,6 +139,45 @@ __device__ __forceinline__ void bwd_sample(const RenderParams& P, const float4* 
     bwd_finish<VT, OP, LIT>(P, tab, rs, lit, corner, S);
 }
 
+// A ray's volume-gradient contributions to the 8 corners of one cell,
+// summed while its samples stay in that cell (at half-voxel steps most
+// cells hold two or more consecutive samples) and added to dV when the ray
+// moves to another cell or ends.
+struct DvRun {
+    int c[3] = {INT_MIN, 0, 0};     // cell, c[0] = INT_MIN when empty
+    float w[8];                     // corner (x + 2y + 4z) contributions
+};
+
+__device__ __forceinline__ void dv_flush(const RenderParams& P, const BackwardParams& B, DvRun& r) {
+    if (r.c[0] == INT_MIN) return;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        if (r.w[q] == 0.0f) continue;
+        int x = clampi(r.c[0] + (q & 1), 0, P.nx - 1);
+        int y = clampi(r.c[1] + ((q >> 1) & 1), 0, P.ny - 1);
+        int z = clampi(r.c[2] + (q >> 2), 0, P.nz - 1);
+        unsafeAtomicAdd(&B.dvol[((long long)z * P.ny + y) * P.nx + x], r.w[q]);
+    }
+    r.c[0] = INT_MIN;
+}
+
+__device__ __forceinline__ void dv_add(const RenderParams& P, const BackwardParams& B, DvRun& r,
+                                       const Cell& C, float dv) {
+    if (C.c[0] != r.c[0] || C.c[1] != r.c[1] || C.c[2] != r.c[2]) {
+        dv_flush(P, B, r);
+        r.c[0] = C.c[0]; r.c[1] = C.c[1]; r.c[2] = C.c[2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r.w[q] = 0.0f;
+    }
+    const float fx = C.fr[0], fy = C.fr[1], fz = C.fr[2];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        float w = ((q & 1) ? fx : 1.0f - fx) * (((q >> 1) & 1) ? fy : 1.0f - fy) *
+                  ((q >> 2) ? fz : 1.0f - fz);
+        r.w[q] = fmaf(w, dv, r.w[q]);
+    }
+}
+
 // Reverse of shade(): dL/dc -> dL/d(table rgb) and dL/dG, through the same
 // branches the forward took (max(0, .), the |G| floor).
 __device__ __forceinline__ void shade_adjoint(const RenderParams& P, const BwdSample& S,
@@ -248,8 +287,8 @@ __device__ __forceinline__ void gradient_adjoint(const RenderParams& P, const Ba
 // trilinear weights; the gradient goes back through the operator's taps.
 template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const BackwardParams& Bp,
-                                               float* lds, DtfRun& run, const BwdSample& S,
-                                               const RayShade& rs,
+                                               float* lds, DtfRun& run, DvRun& vrun,
+                                               const BwdSample& S, const RayShade& rs,
                                                float Tk, const float4& g, const float Bk1[3],
                                                float Pk1) {
     float ta = Tk * S.a;
@@ -267,20 +306,8 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
                drgb[2] * (S.e1.z - S.e0.z) + da * (S.e1.w - S.e0.w);
     float dv = du * P.Mm1 * P.inv_range;
     if (dv == 0.0f) return;
-    const float fx = S.C.fr[0], fy = S.C.fr[1], fz = S.C.fr[2];
-#pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                float w = (cx ? fx : 1.0f - fx) * (cy ? fy : 1.0f - fy) * (cz ? fz : 1.0f - fz);
-                if (w == 0.0f) continue;        // nearest sampling: one corner only
-                int x = clampi(S.C.c[0] + cx, 0, P.nx - 1);
-                int y = clampi(S.C.c[1] + cy, 0, P.ny - 1);
-                int z = clampi(S.C.c[2] + cz, 0, P.nz - 1);
-                unsafeAtomicAdd(&Bp.dvol[((long long)z * P.ny + y) * P.nx + x], w * dv);
-            }
+    // nearest sampling has fraction 0: only corner 0 gets a non-zero weight
+    dv_add(P, Bp, vrun, S.C, dv);
 }
 
 // One workgroup = one 16x16 pixel tile of one view; views own consecutive
@@ -344,6 +371,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
             BwdSample S, Sn;
             float corner[8], cn[8];
             DtfRun run;
+            DvRun vrun;
             bwd_fetch<VT>(P, R, last, S, corner);
             bwd_finish<VT, OP, LIT>(P, tab, rs, true, corner, S);
             for (long long k = last; k >= 0; --k) {
@@ -352,7 +380,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                 if (k < anchor) {
                     Q *= om;
                     float Tk = Q > 0.0f ? Ta / Q : 0.0f;
-                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, S, rs, Tk, g, Bk1, Pk1);
+                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, vrun, S, rs, Tk, g, Bk1, Pk1);
                 }
                 Bk1[0] = fmaf(S.a, S.c[0], om * Bk1[0]);
                 Bk1[1] = fmaf(S.a, S.c[1], om * Bk1[1]);
@@ -365,6 +393,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                 }
             }
             dtf_flush(P, Bp, lds, run);
+            dv_flush(P, Bp, vrun);
         }
     }
     if (Bp.lds_tf) {
