@@ -326,15 +326,15 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
         tab = t;
     }
     if (Bp.lds_tf || Bp.lds_table) __syncthreads();
-    int b = blockIdx.x, v = 0;
-    while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
-    const ViewParams& V = S.v[v];
-    b -= S.block_off[v];
-    int tiles_x = (V.W + kBwdTile - 1) / kBwdTile;
-    int tx = b % tiles_x, ty = b / tiles_x;
+    // views take turns block by block, each view's tiles centre-out (the
+    // grid holds exactly the views' blocks, so every block finds its tile)
+    int b = 0, v = view_of_unit(S, 1, (int)blockIdx.x, b);
+    const ViewParams& V = S.v[v < 0 ? 0 : v];
+    int tiles_x = (V.W + kBwdTile - 1) / kBwdTile, tiles_y = (V.H + kBwdTile - 1) / kBwdTile;
+    int tx = centre_out(b % tiles_x, tiles_x), ty = centre_out(b / tiles_x, tiles_y);
     int px = tx * kBwdTile + (threadIdx.x % kBwdTile);
     int py = ty * kBwdTile + (threadIdx.x / kBwdTile);
-    if (px < V.W && py < V.H) {
+    if (v >= 0 && b < tiles_x * tiles_y && px < V.W && py < V.H) {
         Ray R;
         setup_ray(P, V, px, py, R);
         RayShade rs;

@@ -98,7 +98,7 @@ __host__ __device__ inline int group_grid_blocks(int tiles_x, int tiles_y) {
     return ((gx * gy + 7) / 8) * 8 * kGroupTiles * kGroupTiles;
 }
 
-__device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
+__host__ __device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
     const int per = kGroupTiles * kGroupTiles;
     int gx = (tiles_x + kGroupTiles - 1) / kGroupTiles;
     int xcd = b & 7, q = b >> 3;
@@ -106,6 +106,44 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles_x, int tiles_y) {
     int tx = (g % gx) * kGroupTiles + pos % kGroupTiles;
     int ty = (g / gx) * kGroupTiles + pos / kGroupTiles;
     return (tx < tiles_x && ty < tiles_y) ? ty * tiles_x + tx : -1;
+}
+
+// Work order of the multi-view reverse pass, whose rays are long serial
+// chains (every sample of a ray, one after the other): the long rays
+// through the middle of the volume must not be left to the end.
+//  * Position k of 0 .. n-1 taken centre-out: n/2, n/2 - 1, n/2 + 1, ...
+//    (tile rows from the middle row outwards, each row from its middle).
+//  * view_of_unit: unit j of the grid -> its view and its rank among that
+//    view's units.  Views take turns, one unit each while they have units
+//    left, so every view's first (centre) tiles run before the last tiles
+//    of any view.  View v owns (block_off[v+1] - block_off[v]) / unit
+//    units.  Returns the view, or -1 for j outside the grid.
+// (The forward march keeps its row-major groups: measured faster there.)
+__host__ __device__ inline int centre_out(int k, int n) {
+    const int m = n / 2;
+    return (k & 1) ? m - (k + 1) / 2 : m + k / 2;
+}
+
+__host__ __device__ inline int view_of_unit(const ViewSet& S, int unit, int j, int& rank) {
+    int umax = 0;
+    for (int v = 0; v < S.n; ++v) umax = max(umax, (S.block_off[v + 1] - S.block_off[v]) / unit);
+    auto below = [&](int r) {               // units of rank < r
+        int c = 0;
+        for (int v = 0; v < S.n; ++v) c += min((S.block_off[v + 1] - S.block_off[v]) / unit, r);
+        return c;
+    };
+    if (j < 0 || j >= below(umax)) return -1;
+    int lo = 0, hi = umax;                  // below(lo) <= j < below(hi)
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (below(mid) <= j) lo = mid;
+        else hi = mid;
+    }
+    int o = j - below(lo);
+    rank = lo;
+    for (int v = 0; v < S.n; ++v)
+        if ((S.block_off[v + 1] - S.block_off[v]) / unit > lo && o-- == 0) return v;
+    return -1;
 }
 
 // ---------------------------------------------------------------- ray set-up
