@@ -28,7 +28,7 @@ __global__ __launch_bounds__(64) void raycast_adaptive(RenderParams P) {
     const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
     const double big_step = (double)P.adapt * P.step;
     float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
-    long long j = 0, last = -1;
+    int j = 0, last = -1;
     unsigned evaluated = 0, shaded = 0;
     if (valid && R.K >= 0) {
         double t = R.t_in;

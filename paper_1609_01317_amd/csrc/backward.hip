@@ -89,7 +89,7 @@ struct BwdSample {
 // are issued here and consumed by bwd_finish, so a caller can overlap them
 // with other work).
 template <typename VT>
-__device__ __forceinline__ void bwd_fetch(const RenderParams& P, const Ray& R, long long k,
+__device__ __forceinline__ void bwd_fetch(const RenderParams& P, const Ray& R, int k,
                                           BwdSample& S, float corner[8]) {
     lattice_point(P, R, k, S.C, S.pv);
     const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
@@ -132,7 +132,7 @@ __device__ __forceinline__ void bwd_finish(const RenderParams& P, const float4* 
 
 template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void bwd_sample(const RenderParams& P, const float4* tab, const Ray& R,
-                                           const RayShade& rs, long long k, bool lit,
+                                           const RayShade& rs, int k, bool lit,
                                            BwdSample& S) {
     float corner[8];
     bwd_fetch<VT>(P, R, k, S, corner);
@@ -342,17 +342,17 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
         long long pix = (long long)py * V.W + px;
         rc_aux ax = V.aux[pix];
         float4 g = V.grad[pix];
-        long long last = ax.k_last;
+        int last = ax.k_last;
         if (R.K >= 0 && last >= 0 && last <= R.K) {
             // Anchor: the last index a whose front transmittance T_a is at
             // least kTinyT.  Normally a = last + 1 with T_a = t_final; if the
             // ray went (nearly) opaque, a forward pass finds a instead.
-            long long anchor = last + 1;
+            int anchor = last + 1;
             float Ta = ax.t_final;
             if (!(Ta >= kTinyT)) {
                 float T = 1.0f;
                 anchor = 0;
-                for (long long k = 0; k <= last; ++k) {
+                for (int k = 0; k <= last; ++k) {
                     BwdSample S;
                     bwd_sample<VT, OP, LIT>(P, tab, R, rs, k, false, S);
                     float Tn = T * (1.0f - S.a);
@@ -374,7 +374,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
             DvRun vrun;
             bwd_fetch<VT>(P, R, last, S, corner);
             bwd_finish<VT, OP, LIT>(P, tab, rs, true, corner, S);
-            for (long long k = last; k >= 0; --k) {
+            for (int k = last; k >= 0; --k) {
                 if (!LIT && k > 0) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
                 float om = 1.0f - S.a;
                 if (k < anchor) {

@@ -153,7 +153,7 @@ __host__ __device__ inline int view_of_unit(const ViewSet& S, int unit, int j, i
 struct Ray {
     double o[3], d[3];
     double t_in, t_out;
-    long long K;        // index of the last lattice sample, -1 on a miss
+    int K;              // index of the last lattice sample, -1 on a miss (< 2^24)
     double p0[3], dp[3];    // voxel-space position of sample 0 and step between samples
 };
 
@@ -194,7 +194,7 @@ __device__ inline void setup_ray(const RenderParams& P, const ViewParams& V, int
     R.t_in = tmin;
     R.t_out = tmax;
     R.K = -1;
-    if (hit && tmin <= tmax) R.K = (long long)floor((tmax - tmin) / P.step);
+    if (hit && tmin <= tmax) R.K = (int)floor((tmax - tmin) / P.step);
     for (int a = 0; a < 3; ++a) {
         R.p0[a] = (R.o[a] + tmin * R.d[a]) * P.inv_s[a];
         R.dp[a] = P.step * R.d[a] * P.inv_s[a];
@@ -234,7 +234,7 @@ __device__ __forceinline__ void point_at(const RenderParams& P, const Ray& R, do
 
 // Lattice sample k: p0 + k dp, one FP64 FMA per axis.  Monotone in k, so
 // the cells of samples between two lattice indices lie between theirs.
-__device__ __forceinline__ void lattice_point(const RenderParams& P, const Ray& R, long long k,
+__device__ __forceinline__ void lattice_point(const RenderParams& P, const Ray& R, int k,
                                               Cell& C, double pv[3]) {
     double p[3];
 #pragma unroll
@@ -603,8 +603,8 @@ __device__ __forceinline__ float correct_opacity(const RenderParams& P, float a)
 // 1 - T >= tau).
 struct LaneState {
     float Cr, Cg, Cb, T;
-    long long k;            // next lattice index
-    long long k_term;       // index where early termination fired, -1 if not
+    int k;                  // next lattice index
+    int k_term;             // index where early termination fired, -1 if not
     bool done;
     unsigned evaluated, shaded, direct;
 };
@@ -656,9 +656,9 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
 template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
                                             const LdsSrc<VT>& lsrc, const GlobalSrc<VT>& gsrc,
-                                            bool staged, const Chunk& ch, long long kstop,
+                                            bool staged, const Chunk& ch, int kstop,
                                             const RayShade& rs, LaneState& S) {
-    for (long long k = S.k; k <= kstop; ++k) {
+    for (int k = S.k; k <= kstop; ++k) {
         Cell C;
         double pv[3];
         lattice_point(P, R, k, C, pv);
@@ -699,7 +699,7 @@ constexpr int kSuperMin = 64, kSuperInit = 256;
 // kstop (kstop < S.k when it has none), and the wave-wide bounds of their
 // cells.  Returns false when no lane of the wave has a sample there.
 __device__ __forceinline__ bool chunk_cells(const RenderParams& P, const Ray& R, bool active,
-                                            long long k, double tau, int len, long long& kstop,
+                                            int k, double tau, int len, int& kstop,
                                             int cmin[3], int cmax[3]) {
     double tau_end = tau + (double)len * P.step;
     kstop = -1;
@@ -707,7 +707,7 @@ __device__ __forceinline__ bool chunk_cells(const RenderParams& P, const Ray& R,
     if (active) {
         // which samples fall in a chunk only groups the work: any rounding here is harmless
         double q = ceil((tau_end - R.t_in) * P.inv_step) - 1.0;
-        kstop = q < (double)R.K ? (long long)fmax(q, -1.0) : R.K;
+        kstop = q < (double)R.K ? (int)fmax(q, -1.0) : R.K;
         // the lane(s) defining tau always own at least their next sample
         if (R.t_in + (double)k * P.step < tau_end && kstop < k) kstop = k;
         if (kstop >= k) {
@@ -735,8 +735,8 @@ __device__ __forceinline__ bool chunk_cells(const RenderParams& P, const Ray& R,
 // its cells span at most 64 super-bricks.  Returns true when every one of
 // them is empty; kstop is then this lane's last sample in the chunk.
 __device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const Ray& R, bool active,
-                                                  long long k, double tau, int& len,
-                                                  long long& kstop, int lane) {
+                                                  int k, double tau, int& len,
+                                                  int& kstop, int lane) {
     const int n[3] = {P.nx, P.ny, P.nz};
     for (;; len >>= 1) {
         int cmin[3], cmax[3];
@@ -770,7 +770,7 @@ __device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const R
 // lattice steps before the crossing, so no rounding puts it into a
 // non-empty super-brick.  Those samples have opacity 0 and are skipped.
 // Returns K + 1 when the whole ray is empty.
-__device__ __forceinline__ long long entry_index(const RenderParams& P, const Ray& R) {
+__device__ __forceinline__ int entry_index(const RenderParams& P, const Ray& R) {
     const int n[3] = {P.nx, P.ny, P.nz}, ns[3] = {P.nsx, P.nsy, P.nsz};
     int cell[3], dir[3];
     float kb[3], dk[3];
@@ -794,7 +794,7 @@ __device__ __forceinline__ long long entry_index(const RenderParams& P, const Ra
         if (!(k_enter <= kmax) || cell[a] < 0 || cell[a] >= ns[a]) return R.K + 1;
         kb[a] += dk[a];
     }
-    return max(0ll, (long long)floorf(k_enter) - 2);
+    return max(0, (int)floorf(k_enter) - 2);
 }
 
 // March the 64 rays of this wave together.  `has_ray` is false for lanes
@@ -835,7 +835,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
         // the chunk starts at the earliest pending sample of the wave
         double tau = wave_min_nonneg(active ? R.t_in + (double)S.k * P.step : INFINITY);
         Chunk ch;
-        long long kstop = -1;
+        int kstop = -1;
         if (try_super) {
             // grows with the brick chunk length (up to 1024 after empty chunks)
             int slen = max(len * 8, kSuperInit);

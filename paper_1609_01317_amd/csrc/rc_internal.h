@@ -46,8 +46,10 @@ rc_status hip_fail(hipError_t e, const char* what);
 constexpr int kBrick = 8;
 constexpr int kBrickVox = 512;
 
+// v < 8: bit 0 stays, bit 1 -> 3, bit 2 -> 6 (v | v << 2 | v << 4 puts each
+// bit i at 3i among copies that the mask drops)
 __host__ __device__ inline uint32_t spread3(uint32_t v) {
-    return (v & 1u) | ((v & 2u) << 2) | ((v & 4u) << 4);
+    return (v | (v << 2) | (v << 4)) & 0x49u;
 }
 __host__ __device__ inline uint32_t compact3(uint32_t m) {
     return (m & 1u) | ((m >> 2) & 2u) | ((m >> 4) & 4u);

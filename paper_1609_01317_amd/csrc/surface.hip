@@ -50,8 +50,8 @@ __global__ __launch_bounds__(64) void raycast_surface(RenderParams P, SurfacePar
     Cell C;
     double pv[3];
     // coarse march: the first lattice sample inside the window
-    long long first = -1;
-    for (long long k = 0; k <= R.K; ++k) {
+    int first = -1;
+    for (int k = 0; k <= R.K; ++k) {
         lattice_point(P, R, k, C, pv);
         if (S.range) {
             int b0 = clampi(C.c[0], 0, P.nx - 1) >> 3, b1 = clampi(C.c[1], 0, P.ny - 1) >> 3,
