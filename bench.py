@@ -52,10 +52,12 @@ PROFILE = os.path.join(ROOT, "profiles", "raycast_fwd_c3_orbit.txt")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources and the C header: HBM counters recorded in
-    the profile summary describe these sources only."""
+    """Hash of the sources that define raycast_fwd (the forward kernel, its
+    device code, the shared parameter structs and the C header): HBM
+    counters recorded in the profile summary describe these sources only."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1609_01317_amd", "csrc", "*")))
+    csrc = os.path.join(ROOT, "paper_1609_01317_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in ("march.h", "rc_internal.h", "render.hip")]
     files.append(os.path.join(ROOT, "include", "rc.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
