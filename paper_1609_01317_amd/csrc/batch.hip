@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
                                                      int total, int* __restrict__ counter) {
     extern __shared__ __align__(16) unsigned char lds_all[];
     const int lane = threadIdx.x & 63;
-    unsigned char* lds = lds_all + (threadIdx.x >> 6) * kWaveLdsBytes;
+    unsigned char* lds = lds_all + (threadIdx.x >> 6) * kBatchWaveLdsBytes;
     for (;;) {
         int w = 0;
         if (lane == 0) w = atomicAdd(counter, 1);
@@ -138,19 +138,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
         int tile = w - tile_off[lo];
         const RenderParams& P = items[item];
         switch (kinds[item]) {
-            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, (uint8_t*)lds); break;
-            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, (uint8_t*)lds); break;
-            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, (uint8_t*)lds); break;
-            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, (uint16_t*)lds); break;
-            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, (uint16_t*)lds); break;
-            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, (uint16_t*)lds); break;
-            case 6: render_tile<float, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, (float*)lds); break;
-            case 7: render_tile<float, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, (float*)lds); break;
-            case 8: render_tile<float, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, (float*)lds); break;
+            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 6: render_tile<float, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 7: render_tile<float, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 8: render_tile<float, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
             // unshaded items: no gradient, one instantiation per voxel type
-            case 9: render_tile<uint8_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, (uint8_t*)lds); break;
-            case 10: render_tile<uint16_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, (uint16_t*)lds); break;
-            default: render_tile<float, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, (float*)lds); break;
+            case 9: render_tile<uint8_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            case 10: render_tile<uint16_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
+            default: render_tile<float, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, lds, kBatchWaveLdsBytes); break;
         }
     }
 }
@@ -341,7 +341,7 @@ static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
                            b->total_super, b->d_mask, b->d_super);
     }
     hipLaunchKernelGGL(raycast_batch, dim3(b->grid), dim3(64 * b->cfg.waves_per_wg),
-                       (size_t)kWaveLdsBytes * b->cfg.waves_per_wg, s,
+                       (size_t)kBatchWaveLdsBytes * b->cfg.waves_per_wg, s,
                        b->d_items, b->d_kinds, b->d_tile_off, b->d_order, b->n, b->total_tiles,
                        b->d_counter);
     RC_HIP(hipGetLastError());

@@ -19,12 +19,14 @@
 #pragma once
 
 #include <climits>
+#include <type_traits>
 
 #include "rc_internal.h"
 
 namespace rc {
 
-constexpr int kWaveLdsBytes = 8192;     // LDS box budget per wave
+constexpr int kWaveLdsBytes = 12288;    // LDS box budget per wave (single-image kernels)
+constexpr int kBatchWaveLdsBytes = 8192; // per wave in the batched kernel (measured better there)
 constexpr int kStatSlots = 64;          // per-render counter copies (see render_tile)
 
 __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(t, b - a, a); }
@@ -251,6 +253,7 @@ __device__ __forceinline__ void lattice_point(const RenderParams& P, const Ray& 
 //    LDS offsets).
 template <typename VT>
 struct GlobalSrc {
+    using elem = VT;
     const VT* __restrict__ base;
     int nx, ny, nz, sy, sz;
     __device__ __forceinline__ void offsets(const Cell& C, int ox[4], int oy[4], int oz[4]) const {
@@ -265,6 +268,7 @@ struct GlobalSrc {
 
 template <typename VT>
 struct LdsSrc {
+    using elem = VT;        // the staged element type (see LdsT)
     const VT* base;
     int lo[3];          // box origin (voxel index, may be negative)
     int bx, bxy;        // row and slab strides in elements
@@ -509,10 +513,17 @@ __device__ __forceinline__ void shade(const RenderParams& P, const float4& rgba,
 
 // ---------------------------------------------------------------- LDS staging
 // Stage the voxel box [lo, lo + dim) (dims even, lo even) into LDS as
-// [z][y][x] elements.  Work unit: a 2x2x2 Morton group, which is 8
-// contiguous voxels in the bricked layout (one 16-byte load for u16) and 4
-// x-pairs of the LDS box.  Groups that reach outside the padded brick grid
-// (volume edges) are read voxel by voxel with clamped indices.
+// [z][y][x] elements of type LT.  The Sobel3D and Zucker-Hummel samples
+// read 64 voxels each, so their boxes hold FP32 (each voxel converted once
+// here, not at every read); central differences read 32 and keep the
+// volume's own type (half the LDS bytes per voxel: longer chunks).  Work
+// unit: a 2x2x2 Morton group, which is 8 contiguous voxels in the bricked
+// layout (one 16-byte load for u16) and 4 x-pairs of the LDS box.  Groups
+// that reach outside the padded brick grid (volume edges) are read voxel by
+// voxel with clamped indices.
+template <typename VT, int OP> struct LdsT { using type = float; };
+template <typename VT> struct LdsT<VT, RC_GRAD_CENTRAL> { using type = VT; };
+
 template <typename VT> struct PairT;
 template <> struct PairT<uint8_t> { using type = uint16_t; };
 template <> struct PairT<uint16_t> { using type = uint32_t; };
@@ -523,6 +534,7 @@ template <> struct GroupT<uint8_t> { using type = uint2; };
 template <> struct GroupT<uint16_t> { using type = uint4; };
 template <> struct GroupT<float> { struct type { uint4 a, b; }; };
 
+// A group's 4 x-pairs as they lie in memory (Morton order x + 2y + 4z).
 template <typename VT>
 __device__ __forceinline__ void group_pairs(const typename GroupT<VT>::type& g,
                                             typename PairT<VT>::type p[4]);
@@ -541,8 +553,35 @@ __device__ __forceinline__ void group_pairs<float>(const GroupT<float>::type& g,
     p[2] = make_uint2(g.b.x, g.b.y); p[3] = make_uint2(g.b.z, g.b.w);
 }
 
+// The 8 voxels of a group in Morton order (x + 2y + 4z), as floats.
 template <typename VT>
-__device__ inline void stage_box(const RenderParams& P, VT* lds, const int lo[3], const int dim[3],
+__device__ __forceinline__ void group_values(const typename GroupT<VT>::type& g, float f[8]);
+template <>
+__device__ __forceinline__ void group_values<uint8_t>(const uint2& g, float f[8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f[q] = (float)((g.x >> (8 * q)) & 0xffu);
+        f[4 + q] = (float)((g.y >> (8 * q)) & 0xffu);
+    }
+}
+template <>
+__device__ __forceinline__ void group_values<uint16_t>(const uint4& g, float f[8]) {
+    const unsigned w[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f[2 * q] = (float)(w[q] & 0xffffu);
+        f[2 * q + 1] = (float)(w[q] >> 16);
+    }
+}
+template <>
+__device__ __forceinline__ void group_values<float>(const GroupT<float>::type& g, float f[8]) {
+    const unsigned w[8] = {g.a.x, g.a.y, g.a.z, g.a.w, g.b.x, g.b.y, g.b.z, g.b.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) f[q] = __uint_as_float(w[q]);
+}
+
+template <typename VT, typename LT>
+__device__ inline void stage_box(const RenderParams& P, LT* lds, const int lo[3], const int dim[3],
                                  int lane) {
     using G = typename GroupT<VT>::type;
     using PT = typename PairT<VT>::type;
@@ -562,12 +601,22 @@ __device__ inline void stage_box(const RenderParams& P, VT* lds, const int lo[3]
             int z0 = lo[2] + 2 * iz;
             if (xy_in && z0 >= 0 && z0 + 1 < zmax) {
                 const G* src = (const G*)(vox + oxy + off_z(z0, P.sz));
-                PT p[4];
-                group_pairs<VT>(*src, p);
-                *(PT*)(lds + l0) = p[0];
-                *(PT*)(lds + l0 + bx) = p[1];
-                *(PT*)(lds + l0 + bxy) = p[2];
-                *(PT*)(lds + l0 + bxy + bx) = p[3];
+                // l0 and the strides are even: pair-aligned stores
+                if constexpr (std::is_same<LT, float>::value) {
+                    float f[8];
+                    group_values<VT>(*src, f);
+                    *(float2*)(lds + l0) = make_float2(f[0], f[1]);
+                    *(float2*)(lds + l0 + bx) = make_float2(f[2], f[3]);
+                    *(float2*)(lds + l0 + bxy) = make_float2(f[4], f[5]);
+                    *(float2*)(lds + l0 + bxy + bx) = make_float2(f[6], f[7]);
+                } else {
+                    PT p[4];
+                    group_pairs<VT>(*src, p);
+                    *(PT*)(lds + l0) = p[0];
+                    *(PT*)(lds + l0 + bx) = p[1];
+                    *(PT*)(lds + l0 + bxy) = p[2];
+                    *(PT*)(lds + l0 + bxy + bx) = p[3];
+                }
             } else {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
@@ -575,7 +624,7 @@ __device__ inline void stage_box(const RenderParams& P, VT* lds, const int lo[3]
                     int x = clampi(x0 + dx, 0, P.nx - 1), y = clampi(y0 + dy, 0, P.ny - 1),
                         z = clampi(z0 + dz, 0, P.nz - 1);
                     lds[l0 + dz * bxy + dy * bx + dx] =
-                        vox[off_x(x) + off_y(y, P.sy) + off_z(z, P.sz)];
+                        (LT)vox[off_x(x) + off_y(y, P.sy) + off_z(z, P.sz)];
                 }
             }
         }
@@ -629,7 +678,8 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     int ox[4], oy[4], oz[4];
     src.offsets(C, ox, oy, oz);
     float corner[8];
-    float v = sample_value<VT>(src.base, ox, oy, oz, C, corner);
+    using ET = typename Src::elem;          // element type of the source
+    float v = sample_value<ET>(src.base, ox, oy, oz, C, corner);
     float4 rgba = tf_lookup(P, v);
     float a = rgba.w;
     if (a == 0.0f) return false;
@@ -638,7 +688,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     float c[3] = {rgba.x, rgba.y, rgba.z};
     if (LIT) {
         float g[3];
-        gradient<VT, OP, true>(P, src.base, ox, oy, oz, C, g, corner);
+        gradient<ET, OP, true>(P, src.base, ox, oy, oz, C, g, corner);
         shade(P, rgba, g, pv, rs, c);
     }
     float ta = S.T * a;
@@ -655,7 +705,8 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
 // 4x4x4 footprint lies inside the box, else the bricked volume.
 template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
-                                            const LdsSrc<VT>& lsrc, const GlobalSrc<VT>& gsrc,
+                                            const LdsSrc<typename LdsT<VT, OP>::type>& lsrc,
+                                            const GlobalSrc<VT>& gsrc,
                                             bool staged, const Chunk& ch, int kstop,
                                             const RayShade& rs, LaneState& S) {
     for (int k = S.k; k <= kstop; ++k) {
@@ -801,8 +852,8 @@ __device__ __forceinline__ int entry_index(const RenderParams& P, const Ray& R) 
 // outside the image; they still take part in the wave-wide steps.  LIT must
 // equal (P.shade != RC_SHADE_NONE).
 template <typename VT, int OP, bool LIT>
-__device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_ray, VT* lds,
-                                  int lane, MarchOut& M) {
+__device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_ray, void* lds_raw,
+                                  int lds_bytes, int lane, MarchOut& M) {
     LaneState S;
     S.Cr = S.Cg = S.Cb = 0.f;
     S.T = 1.0f;
@@ -819,7 +870,9 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     RayShade rs;
     ray_shade(P, R, rs);
     const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
-    const int cap = kWaveLdsBytes / (int)sizeof(VT);
+    using LT = typename LdsT<VT, OP>::type;
+    LT* lds = (LT*)lds_raw;
+    const int cap = lds_bytes / (int)sizeof(LT);
     int len = kChunkInit;
     // a super-chunk is tried at the start and after every empty chunk
     bool try_super = P.skip && P.super_empty != nullptr;
@@ -897,12 +950,12 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
         }
         if (fits) {
             ++n_staged;
-            stage_box<VT>(P, lds, ch.lo, ch.dim, lane);
+            stage_box<VT, LT>(P, lds, ch.lo, ch.dim, lane);
             wave_lds_sync();
         } else {
             ++n_direct;
         }
-        LdsSrc<VT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1]};
+        LdsSrc<LT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1]};
         if (active && kstop >= S.k)
             run_samples<VT, OP, LIT>(P, R, lsrc, gsrc, fits, ch, kstop, rs, S);
         if (fits) wave_lds_sync();
@@ -925,7 +978,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
 // in the wave-wide steps without a ray.
 template <typename VT, int OP, bool LIT>
 __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, int tile, int lane,
-                                   VT* lds) {
+                                   void* lds, int lds_bytes) {
     const int tw = V.tile_w, th = 64 / V.tile_w;
     int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
     int px = tx * tw + (lane % tw), py = ty * th + (lane / tw);
@@ -936,7 +989,7 @@ __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, i
     for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = R.p0[a] = R.dp[a] = 0.0;
     if (valid) setup_ray(P, V, px, py, R);
     MarchOut M;
-    march_wave<VT, OP, LIT>(P, R, valid, lds, lane, M);
+    march_wave<VT, OP, LIT>(P, R, valid, lds, lds_bytes, lane, M);
     if (valid) {
         long long pix = (long long)py * V.W + px;
         V.out[pix] = M.rgba;

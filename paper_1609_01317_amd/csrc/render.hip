@@ -107,7 +107,7 @@ raycast_fwd(RenderParams P) {
     __shared__ __align__(16) unsigned char lds[lds_for(LIT)];
     const ViewParams& V = P.view;
     int tile = tile_of_block(blockIdx.x, V.tiles_x, V.n_tiles / V.tiles_x);
-    if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, (VT*)lds);
+    if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, lds, lds_for(LIT));
 }
 
 // Several views of one volume: each view owns a run of blocks (a multiple of
@@ -120,7 +120,7 @@ raycast_views(RenderParams P, ViewSet S) {
     while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
     const ViewParams& V = S.v[v];
     int tile = tile_of_block(b - S.block_off[v], V.tiles_x, V.n_tiles / V.tiles_x);
-    if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, (VT*)lds);
+    if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, lds, lds_for(LIT));
 }
 
 // ---------------------------------------------------------------- counters
