@@ -18,7 +18,6 @@ roofline position, and the FP64 CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
