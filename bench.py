@@ -320,21 +320,26 @@ def run_surface(args, sc=None, vol=None, tf=None):
             "surface_pixels_view0": hits}
 
 
-def cpu_baseline(sc, counts_unused=None):
-    """FP64 oracle on one full Sobel3D view of the headline workload."""
+def cpu_baseline(sc, counts):
+    """FP64 oracle on six full Sobel3D views of the headline workload (every
+    sixth view of the orbit), in the metric's unit: the views' lattice samples
+    (the workload size the GPU figure counts, from the counting pass) over the
+    oracle's wall time."""
     import oracle
     v = oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
-    cam = sc.cameras[0]
     opt = c3_options(sc, "sobel3d")
+    views = list(range(0, len(sc.cameras), 6))
     t0 = time.perf_counter()
-    r = oracle.render(v, cam, sc.tf, sc.shading, opt)
+    for i in views:
+        oracle.render(v, sc.cameras[i], sc.tf, sc.shading, opt)
     dt = time.perf_counter() - t0
-    lattice = int((r["k_last"] + 1).sum())
+    lattice = int(sum(counts["sobel3d"][i, 0] for i in views))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(lattice / dt / 1e9, 6), "unit": "Gsamples/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"one full 1024x1024 Sobel3D view (azimuth 0) of the 512^3 u16 orbit: "
-                      f"{lattice} lattice samples in {dt:.1f} s"}
+            "sample": f"{len(views)} full 1024x1024 Sobel3D views (every sixth view of the "
+                      f"orbit) of the 512^3 u16 workload: {lattice} lattice samples in "
+                      f"{dt:.1f} s"}
 
 
 def calib_copy():
@@ -418,7 +423,7 @@ def main():
         result["surface"] = run_surface(args, sc, vol, tf)
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
-        result["cpu_baseline"] = cpu_baseline(sc)
+        result["cpu_baseline"] = cpu_baseline(sc, counts)
     print(json.dumps(result), flush=True)
 
 
