@@ -7,8 +7,12 @@ step 0.5, early ray termination at 0.99 and 8^3-brick empty-space skipping.
 
 One step = the whole hot path over that input: re-ingest the resident
 linear volume into the brick layout, rebuild the brick value ranges, then
-108 renders (36 views x 3 operators), each with its own empty-brick mask.
-`value` = lattice samples of one step / step time (Gsamples/s).
+render the 108 views (36 views x 3 operators): each operator's orbit is a
+render list built once before timing and rendered in one persistent
+batched launch per step, with its empty-brick masks recomputed.  `value` =
+lattice samples of one step / step time (Gsamples/s).  The single-image
+path (one rc_render per view) is timed beside it, and two views per
+operator are checked bit for bit against it.
 
 Also reported (outside `value`): per-operator rates and frame rates, the
 differentiable form (16 views of a 128^3 f32 volume, forward and
@@ -51,12 +55,14 @@ PROFILE = os.path.join(ROOT, "profiles", "raycast_fwd_c3_orbit.txt")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the sources that define raycast_fwd (the forward kernel, its
-    device code, the shared parameter structs and the C header): HBM
-    counters recorded in the profile summary describe these sources only."""
+    """Hash of the sources that define the measured forward kernels
+    (raycast_batch and raycast_fwd: the batch and render sources, the march,
+    the shared parameter structs and the C header): HBM counters recorded in
+    the profile summary describe these sources only."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1609_01317_amd", "csrc")
-    files = [os.path.join(csrc, f) for f in ("march.h", "rc_internal.h", "render.hip")]
+    files = [os.path.join(csrc, f) for f in ("batch.hip", "march.h", "rc_internal.h",
+                                               "render.hip")]
     files.append(os.path.join(ROOT, "include", "rc.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -65,17 +71,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(op: str):
-    """HBM bytes per launch of raycast_fwd<uint16, op> from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
-    sources changed since the counters were taken."""
+def recorded_traffic():
+    """HBM bytes per launch of raycast_batch (mean over the orbit launches of
+    the three operators) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel sources changed since the counters were
+    taken."""
     if not os.path.exists(PROFILE):
         return None
     text = open(PROFILE).read()
     m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
     if not m or m.group(1) != kernel_source_hash():
         return None
-    m = re.search(r"hbm_bytes_per_launch\s+" + re.escape(op) + r":\s*([0-9.eE+]+)", text)
+    m = re.search(r"hbm_bytes_per_launch\s+raycast_batch:\s*([0-9.eE+]+)", text)
     return float(m.group(1)) if m else None
 
 
@@ -91,30 +98,48 @@ def c3_options(sc, op):
     return dict(sc.options, gradient_op=op)
 
 
+def timed_pass(fn):
+    """One call of fn bracketed by HIP events on the current stream (ms)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    return e0, e1
+
+
 def run_c3(args):
+    """The orbit of each operator is one render list of its views (an rc_batch
+    built once, before timing: cameras, outputs and options are fixed); a
+    step re-ingests the volume, rebuilds the brick ranges and renders the
+    three lists, each in one persistent launch (empty masks recomputed per
+    render, as rc_render does)."""
     sc = W.config_c3(n_views=args.views)
     log(f"bench: c3 volume {sc.volume.shape} {sc.volume.dtype}, {len(sc.cameras)} views")
     src = to_dev(sc.volume)
     vol = rc.rc_create_volume(src, sc.spacing, sc.vmin, sc.vmax)
     rc.rc_build_bricks(vol, 8)
     tf = to_dev(sc.tf)
-    out = torch.empty((sc.cameras[0]["height"], sc.cameras[0]["width"], 4),
-                      dtype=torch.float32, device="cuda")
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    out = torch.empty((H, Wd, 4), dtype=torch.float32, device="cuda")
     opts = {op: c3_options(sc, op) for op in OPS}
+    outs = {op: [torch.empty((H, Wd, 4), dtype=torch.float32, device="cuda")
+                 for _ in sc.cameras] for op in OPS}
+    items = {op: [{"vol": vol, "camera": cam, "tf": tf, "shading": sc.shading,
+                   "options": opts[op], "out": o} for cam, o in zip(sc.cameras, outs[op])]
+             for op in OPS}
+    cache = os.path.join(ROOT, "_build", "batch_autotune.jsonl")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    cfgs = {op: rc.rc_batch_autotune(items[op], cache) for op in OPS}
+    batches = {op: rc.rc_batch_create(items[op], cfgs[op]) for op in OPS}
 
     def step(events=None):
         rc.rc_update_volume(vol, src)
         rc.rc_build_bricks(vol, 8)
         for op in OPS:
-            for cam in sc.cameras:
-                if events is not None:
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e0.record()
-                rc.rc_render(vol, cam, tf, sc.shading, opts[op], out=out)
-                if events is not None:
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e1.record()
-                    events[op].append((e0, e1))
+            if events is None:
+                rc.rc_batch_render(batches[op])
+            else:
+                events[op].append(timed_pass(lambda: rc.rc_batch_render(batches[op])))
 
     for _ in range(args.warmup):
         step()
@@ -129,7 +154,15 @@ def run_c3(args):
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     render_ms = {op: [a.elapsed_time(b) for a, b in events[op]] for op in OPS}
 
-    # untimed counting pass: lattice / evaluated / shaded samples per view
+    # untimed: the single-image path (one rc_render per view), and the
+    # counting pass (lattice / evaluated / shaded samples per view)
+    single = {op: [] for op in OPS}
+    for op in OPS:
+        for cam in sc.cameras:
+            single[op].append(timed_pass(
+                lambda: rc.rc_render(vol, cam, tf, sc.shading, opts[op], out=out)))
+    torch.cuda.synchronize()
+    single_ms = {op: [a.elapsed_time(b) for a, b in single[op]] for op in OPS}
     counts = {}
     for op in OPS:
         st = rc.new_stats()
@@ -140,25 +173,38 @@ def run_c3(args):
             per_view.append(st.cpu().numpy().astype(np.int64))
         counts[op] = np.array(per_view)
     torch.cuda.synchronize()
-    return sc, vol, tf, ms_per_step, render_ms, counts
+    # the orbit renders are checked bit for bit against single renders
+    for op in OPS:
+        for i in (0, len(sc.cameras) // 2):
+            rc.rc_render(vol, sc.cameras[i], tf, sc.shading, opts[op], out=out)
+            if not torch.equal(out, outs[op][i]):
+                raise RuntimeError(f"bench: batched {op} view {i} differs from rc_render")
+    return sc, vol, tf, ms_per_step, render_ms, single_ms, counts, cfgs
 
 
 def roofline(render_ms, counts):
-    """Dominant kernel: the operator whose renders take the most time."""
-    op = max(OPS, key=lambda o: sum(render_ms[o]))
-    c = counts[op]
-    evaluated, shaded = c[:, 1].astype(float), c[:, 2].astype(float)
-    flops = FLOPS_VALUE * (evaluated - shaded) + FLOPS_SHADED[op] * shaded
-    avg_ms = float(np.mean(render_ms[op]))
-    achieved = float(flops.mean()) / (avg_ms * 1e-3) / 1e12
-    return op, {
+    """Dominant kernel: raycast_batch, one launch per operator's orbit; the
+    figures are per launch averaged over the three operators' launches."""
+    flops_total = 0.0
+    bytes_total = 0.0
+    for op in OPS:
+        c = counts[op]
+        evaluated, shaded = c[:, 1].astype(float), c[:, 2].astype(float)
+        flops_total += float((FLOPS_VALUE * (evaluated - shaded) + FLOPS_SHADED[op] * shaded).sum())
+        bytes_total += float(
+            2 * (VOXELS_VALUE * (evaluated - shaded) + VOXELS_SHADED[op] * shaded).sum())
+    launches = len(OPS)
+    avg_ms = float(np.mean([np.mean(render_ms[op]) for op in OPS]))
+    flops = flops_total / launches
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    return {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-        "traffic": recorded_traffic(op),
-        "kernel": f"raycast_fwd<uint16, {op}>", "avg_launch_ms": round(avg_ms, 4),
-        "algorithmic_flops_per_launch": float(flops.mean()),
-        "algorithmic_voxel_bytes_per_launch": float(
-            2 * (VOXELS_VALUE * (evaluated - shaded) + VOXELS_SHADED[op] * shaded).mean()),
+        "traffic": recorded_traffic(),
+        "kernel": "raycast_batch (one launch = one operator's 36-view orbit)",
+        "avg_launch_ms": round(avg_ms, 4),
+        "algorithmic_flops_per_launch": flops,
+        "algorithmic_voxel_bytes_per_launch": bytes_total / launches,
     }
 
 
@@ -382,7 +428,7 @@ def main():
         print(json.dumps(fn(args)), flush=True)
         return
 
-    sc, vol, tf, ms_per_step, render_ms, counts = run_c3(args)
+    sc, vol, tf, ms_per_step, render_ms, single_ms, counts, cfgs = run_c3(args)
     lattice_step = int(sum(counts[op][:, 0].sum() for op in OPS))
     value = lattice_step / (ms_per_step * 1e-3) / 1e9
     per_op = {}
@@ -390,7 +436,11 @@ def main():
         ms = float(np.sum(render_ms[op])) / args.steps
         lat = int(counts[op][:, 0].sum())
         ev = int(counts[op][:, 1].sum())
+        ms1 = float(np.sum(single_ms[op]))
         per_op[op] = {"orbit_ms": round(ms, 3), "fps": round(len(sc.cameras) / (ms * 1e-3), 1),
+                      "batch_config": cfgs[op],
+                      "single_image_orbit_ms": round(ms1, 3),
+                      "single_image_ms_per_view": round(ms1 / len(sc.cameras), 4),
                       "lattice_gsamples_s": round(lat / (ms * 1e-3) / 1e9, 3),
                       "evaluated_gsamples_s": round(ev / (ms * 1e-3) / 1e9, 3),
                       "lattice_samples": lat, "evaluated_samples": ev,
@@ -399,7 +449,7 @@ def main():
                       "chunks_empty": int(counts[op][:, 5].sum()),
                       "chunks_direct": int(counts[op][:, 6].sum()),
                       "samples_direct": int(counts[op][:, 7].sum())}
-    dom_op, roof = roofline(render_ms, counts)
+    roof = roofline(render_ms, counts)
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -408,7 +458,9 @@ def main():
         "config": {"workload": "512^3 u16 CT-like phantom (24 ellipsoids, 12-bit, noise 20) -> "
                                "1024^2 perspective 60 deg, 36-view orbit at 10 deg steps x "
                                "{central difference, Sobel3D, Zucker-Hummel}, step 0.5, ERT 0.99, "
-                               "8^3-brick skipping; step = ingest + brick ranges + 108 renders",
+                               "8^3-brick skipping; step = ingest + brick ranges + the three "
+                               "operators' orbits, each one persistent batched launch of its 36 "
+                               "views",
                    "views": len(sc.cameras), "image": [1024, 1024], "volume": [512, 512, 512],
                    "lattice_samples_per_step": lattice_step},
         "per_operator": per_op,

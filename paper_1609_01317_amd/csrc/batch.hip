@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <map>
 #include <numeric>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -209,6 +211,8 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     std::vector<RenderParams> P(n);
     std::vector<int> kinds(n), tiles(n);
     std::vector<MaskJob> jobs;
+    std::vector<int> job_of(n, -1);        // items of one volume and table share a mask
+    std::map<std::tuple<const void*, const void*, int>, int> job_index;
     long long total_bricks = 0, total_prefix = 0, total_super = 0;
     for (int i = 0; i < n; ++i) {
         const rc_batch_item& it = items[i];
@@ -226,6 +230,15 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
                                                 : (int)it.vol->dtype * 3 + it.opt.gradient_op;
         tiles[i] = P[i].view.n_tiles;
         if (it.opt.skip_empty) {
+            const auto key = std::make_tuple((const void*)it.vol, (const void*)it.tf_rgba_dev,
+                                             it.tf_len);
+            const auto found = job_index.find(key);
+            if (found != job_index.end()) {
+                job_of[i] = found->second;
+                continue;
+            }
+            job_of[i] = (int)jobs.size();
+            job_index.emplace(key, job_of[i]);
             MaskJob J;
             J.range = it.vol->brick_range;
             J.tf = (const float4*)it.tf_rgba_dev;
@@ -296,11 +309,10 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     b->d_prefix = (int*)(base + o_prefix);
     b->d_mask = (uint8_t*)(base + o_mask);
     b->d_super = (uint8_t*)(base + o_super);
-    for (int i = 0, j = 0; i < n; ++i)
-        if (items[i].opt.skip_empty) {
-            P[i].empty = b->d_mask + jobs[j].brick_off;
-            P[i].super_empty = b->d_super + jobs[j].super_off;
-            ++j;
+    for (int i = 0; i < n; ++i)
+        if (job_of[i] >= 0) {
+            P[i].empty = b->d_mask + jobs[job_of[i]].brick_off;
+            P[i].super_empty = b->d_super + jobs[job_of[i]].super_off;
         }
     hipStream_t s = (hipStream_t)stream;
     e = hipMemcpyAsync(b->d_items, P.data(), sizeof(RenderParams) * n, hipMemcpyHostToDevice, s);

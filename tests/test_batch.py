@@ -84,6 +84,40 @@ def test_batch_equals_single_renders(cfg):
         assert not bad.any(), err
 
 
+def test_items_sharing_volume_and_table():
+    """Orbit-style batches: several views of one volume and table (their
+    empty-brick masks are computed once and shared), mixed with items that
+    share only the volume or only the table.  Every output equals its own
+    rc_render bit for bit."""
+    sc = W.config_small(seed=48, dims=(45, 38, 33), dtype=np.uint16, image=(48, 40),
+                        op="sobel3d", ert=0.99, skip=True)
+    vol = gpu_volume(sc, bricks=True)
+    tf = to_dev(sc.tf)
+    tf2 = to_dev(W.tf_ramps(sc.tf.shape[0], seed=148, alpha_max=0.3,
+                            hi=max(0.06, 0.9 * float(sc.volume.max()) / 4095.0)))
+    sc2 = W.config_small(seed=49, dims=(30, 28, 26), dtype=np.uint16, image=(32, 32),
+                         op="sobel3d", skip=True)
+    vol2 = gpu_volume(sc2, bricks=True)
+    items = []
+    for az, v, t in ((0.0, vol, tf), (40.0, vol, tf), (95.0, vol, tf2), (150.0, vol, tf),
+                     (200.0, vol2, tf), (260.0, vol, tf2), (300.0, vol, tf)):
+        dims = sc.volume.shape[::-1] if v is vol else sc2.volume.shape[::-1]
+        cam = W.orbit_camera(tuple(dims), (1, 1, 1), az, 20.0, 48, 40)
+        items.append({"vol": v, "camera": cam, "tf": t, "shading": sc.shading,
+                      "options": sc.options,
+                      "out": torch.full((40, 48, 4), -1.0, device="cuda"),
+                      "aux": rc.new_aux(cam)})
+    refs = _reference(items)
+    rc.rc_render_batch(items)
+    torch.cuda.synchronize()
+    lit = 0
+    for it, (img, aux) in zip(items, refs):
+        assert torch.equal(it["out"], img)
+        assert torch.equal(it["aux"], aux)
+        lit += int((img[..., 3] > 1e-3).sum())
+    assert lit > 500
+
+
 def test_graph_replay_matches_eager():
     scenes = _scenes()
     items = _items(scenes)
