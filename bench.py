@@ -51,7 +51,7 @@ VOXELS_VALUE = 8
 VOXELS_SHADED = {"central": 32, "sobel3d": 64, "zucker_hummel": 64}
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "raycast_fwd_c3_orbit.txt")
+PROFILE = os.path.join(ROOT, "profiles", "raycast_batch_c3_orbit.txt")
 
 
 def kernel_source_hash() -> str:
