@@ -242,15 +242,19 @@ typedef struct {
 typedef struct rc_batch rc_batch;   /* opaque: descriptors, queue, masks, captured graph */
 
 /* Validate every item as rc_render would, upload the descriptors and
- * allocate the queue and mask scratch.  cfg NULL = {8, 1, 8, 1}.  The
+ * allocate the queue and mask scratch.  cfg NULL = {8, 1, 8, 1}.  Items
+ * that share a volume and a table (the views of an orbit) share one
+ * empty-brick mask.  The images are bit-identical to rc_render's.  The
  * items' volumes, tables and outputs must outlive the batch.
  * Errors: RC_E_INVALID (with the failing item index in rc_last_error),
  * RC_E_STATE, RC_E_OOM, RC_E_DEVICE. */
 rc_status rc_batch_create(const rc_batch_item* items, int n, const rc_batch_config* cfg,
                           void* stream, rc_batch** out);
 
-/* Render every item with one persistent launch (plus two small mask
- * kernels and a queue reset).  use_graph = 1 captures that sequence into a
+/* Render every item with one persistent launch (plus three small mask
+ * kernels and a queue reset): resident waves take (item, tile) work from
+ * a queue, which keeps the compute units fuller than one launch per image
+ * (an orbit of many views renders faster this way than view by view).  use_graph = 1 captures that sequence into a
  * HIP graph on the first call and replays it afterwards (stream must not be
  * NULL); use_graph = 0 launches eagerly.  Errors: RC_E_INVALID, RC_E_DEVICE. */
 rc_status rc_batch_render(rc_batch* b, int use_graph, void* stream);
