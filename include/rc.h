@@ -278,7 +278,10 @@ rc_status rc_batch_autotune(const rc_batch_item* items, int n, const char* cache
  * Several views of one volume.  The same volume, table, shading and options
  * rendered from n_views cameras with one launch per 16 views, so small
  * images share the GPU.  Equivalent to n_views rc_render /
- * rc_render_backward calls (Section 3.10: rays are independent).
+ * rc_render_backward calls (Section 3.10: rays are independent).  The
+ * forward goes through the persistent kernel of the batch API: its images
+ * are bit-identical to rc_render's.  Adaptive sampling is rc_render only
+ * (RC_E_UNSUPPORTED).
  * ---------------------------------------------------------------------- */
 /*   cams      host array [n_views]
  *   out_rgba  host array [n_views] of device pointers, [H_v][W_v][4] each

@@ -369,6 +369,29 @@ static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
     return RC_OK;
 }
 
+// Items already in device memory (built there by the caller's own kernel):
+// the queue reset and the persistent launch, one wave per workgroup and
+// three resident per SIMD.
+rc_status rc::launch_batch_items(const RenderParams* items, const int* kinds, const int* tile_off,
+                             const int* order, int n, int total, int* counter, int lds_bytes,
+                             hipStream_t s) {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cus[dev] == 0) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c < 1)
+            c = 256;
+        cus[dev] = c;
+    }
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(raycast_batch, dim3((unsigned)(cus[dev] * 12)), dim3(64), (size_t)lds_bytes,
+                       s, items, kinds, tile_off, order, n, total, counter, lds_bytes);
+    RC_HIP(hipGetLastError());
+    return RC_OK;
+}
+
 extern "C" rc_status rc_batch_render(rc_batch* b, int use_graph, void* stream) {
     if (!b) return fail(RC_E_INVALID, "rc_batch_render: batch is NULL");
     hipStream_t s = (hipStream_t)stream;

@@ -143,6 +143,12 @@ size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
 void set_tiling(ViewParams& V, int tile_w);     // tile_w in {4, 8, 16, 32, 64}
 void fill_view(ViewParams& V, const rc_camera* cam);
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
+// The persistent batched kernel over n items already in device memory
+// (queue reset included); total = the items' tiles, kinds/order as in
+// rc_batch_create.
+rc_status launch_batch_items(const RenderParams* items, const int* kinds, const int* tile_off,
+                             const int* order, int n, int total, int* counter, int lds_bytes,
+                             hipStream_t s);
 // per-lane adaptive-step march (P.adapt > 1)
 rc_status launch_adaptive(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
 

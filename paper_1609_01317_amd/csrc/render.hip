@@ -110,17 +110,30 @@ raycast_fwd(RenderParams P) {
     if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, lds, lds_for(LIT));
 }
 
-// Several views of one volume: each view owns a run of blocks (a multiple of
-// the XCD group size, so the group dealing above holds inside every view).
-template <typename VT, int OP, bool LIT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(LIT)))) void
-raycast_views(RenderParams P, ViewSet S) {
-    __shared__ __align__(16) unsigned char lds[lds_for(LIT)];
-    int b = blockIdx.x, v = 0;
-    while (v + 1 < S.n && S.block_off[v + 1] <= b) ++v;
-    const ViewParams& V = S.v[v];
-    int tile = tile_of_block(b - S.block_off[v], V.tiles_x, V.n_tiles / V.tiles_x);
-    if (tile >= 0) render_tile<VT, OP, LIT>(P, V, tile, threadIdx.x, lds, lds_for(LIT));
+// Several views of one volume go through the persistent batched kernel: one
+// item per view, written to device memory by this single-workgroup kernel
+// from the views passed as arguments (no host copy, no synchronisation).
+__global__ __launch_bounds__(64) void pack_views(RenderParams P, ViewSet S, int kind,
+                                                 RenderParams* __restrict__ items,
+                                                 int* __restrict__ kinds,
+                                                 int* __restrict__ tile_off,
+                                                 int* __restrict__ order) {
+    const int i = threadIdx.x;
+    if (i < S.n) {
+        RenderParams q = P;
+        q.view = S.v[i];
+        items[i] = q;
+        kinds[i] = kind;
+        order[i] = i;
+    }
+    if (i == 0) {
+        int t = 0;
+        for (int j = 0; j < S.n; ++j) {
+            tile_off[j] = t;
+            t += S.v[j].n_tiles;
+        }
+        tile_off[S.n] = t;
+    }
 }
 
 // ---------------------------------------------------------------- counters
@@ -159,29 +172,6 @@ rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t
     if (dt == RC_U8) launch_fwd_t<uint8_t>(P, op, st);
     else if (dt == RC_U16) launch_fwd_t<uint16_t>(P, op, st);
     else launch_fwd_t<float>(P, op, st);
-    RC_HIP(hipGetLastError());
-    return RC_OK;
-}
-
-template <typename VT>
-static void launch_views_t(const RenderParams& P, const ViewSet& S, int op, hipStream_t st) {
-    dim3 grid((unsigned)S.block_off[S.n]), block(64);
-    if (P.shade == RC_SHADE_NONE)
-        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_CENTRAL, false>), grid, block, 0, st, P, S);
-    else if (op == RC_GRAD_CENTRAL)
-        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_CENTRAL, true>), grid, block, 0, st, P, S);
-    else if (op == RC_GRAD_SOBEL3D)
-        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_SOBEL3D, true>), grid, block, 0, st, P, S);
-    else
-        hipLaunchKernelGGL((raycast_views<VT, RC_GRAD_ZUCKER_HUMMEL, true>), grid, block, 0, st, P,
-                           S);
-}
-
-static rc_status launch_views(const RenderParams& P, const ViewSet& S, rc_dtype dt, int op,
-                              hipStream_t st) {
-    if (dt == RC_U8) launch_views_t<uint8_t>(P, S, op, st);
-    else if (dt == RC_U16) launch_views_t<uint16_t>(P, S, op, st);
-    else launch_views_t<float>(P, S, op, st);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }
@@ -468,36 +458,55 @@ extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, 
     hipStream_t s = (hipStream_t)stream;
     RenderParams P;
     fill_render_params(P, v, &cams[0], tf_rgba_dev, tf_len, sh, opt);
-    rc_status st = RC_OK;
+    const bool lit = sh->model != RC_SHADE_NONE;
+    const int kind = lit ? (int)v->dtype * 3 + opt->gradient_op : 9 + (int)v->dtype;
+    const int lds_bytes =
+        lit && opt->gradient_op != RC_GRAD_CENTRAL ? kWaveLdsBytes : kBatchWaveLdsBytes;
+    // scratch: the items of one launch, then their kinds, tile offsets,
+    // order and the work counter, then the skip masks
+    const size_t items_bytes = ((sizeof(RenderParams) * kMaxViews + 255) / 256) * 256;
+    const size_t queue_bytes = 256 * 4;
+    size_t mask_bytes = 0, super_bytes = 0, skip_bytes = 0;
+    if (opt->skip_empty) skip_bytes = skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes);
     void* scratch = nullptr;
+    RC_HIP(hipMallocAsync(&scratch, items_bytes + queue_bytes + skip_bytes, s));
+    char* base = (char*)scratch;
+    RenderParams* items = (RenderParams*)base;
+    int* kinds = (int*)(base + items_bytes);
+    int* tile_off = (int*)(base + items_bytes + 256);
+    int* order = (int*)(base + items_bytes + 512);
+    int* counter = (int*)(base + items_bytes + 768);
+    rc_status st = RC_OK;
     if (opt->skip_empty) {
-        size_t mask_bytes, super_bytes;
-        RC_HIP(hipMallocAsync(&scratch, skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes),
-                              s));
-        P.empty = (uint8_t*)scratch;
+        char* sk = base + items_bytes + queue_bytes;
+        P.empty = (uint8_t*)sk;
         P.super_empty = P.empty + mask_bytes;
         st = launch_empty_mask(v, tf_rgba_dev, tf_len, (uint8_t*)P.empty,
-                               (uint8_t*)P.super_empty,
-                               (int*)((char*)scratch + mask_bytes + super_bytes), s);
+                               (uint8_t*)P.super_empty, (int*)(sk + mask_bytes + super_bytes), s);
     }
     for (int first = 0; st == RC_OK && first < n_views; first += kMaxViews) {
         ViewSet S;
         S.n = n_views - first < kMaxViews ? n_views - first : kMaxViews;
-        int off = 0;
+        int total = 0;
         for (int j = 0; j < S.n; ++j) {
             ViewParams& V = S.v[j];
             fill_view(V, &cams[first + j]);
             V.out = (float4*)out_rgba[first + j];
             V.aux = aux ? aux[first + j] : nullptr;
-            S.block_off[j] = off;
-            off += group_grid_blocks(V.tiles_x, V.n_tiles / V.tiles_x);
+            S.block_off[j] = total;
+            total += V.n_tiles;
         }
-        S.block_off[S.n] = off;
-        st = launch_views(P, S, v->dtype, opt->gradient_op, s);
+        S.block_off[S.n] = total;
+        hipLaunchKernelGGL(pack_views, dim3(1), dim3(64), 0, s, P, S, kind, items, kinds,
+                           tile_off, order);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            st = hip_fail(e, "pack_views");
+            break;
+        }
+        st = launch_batch_items(items, kinds, tile_off, order, S.n, total, counter, lds_bytes, s);
     }
-    if (scratch) {
-        hipError_t e = hipFreeAsync(scratch, s);
-        if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
-    }
+    hipError_t e = hipFreeAsync(scratch, s);
+    if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return st;
 }
