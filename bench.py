@@ -22,6 +22,7 @@ roofline position, and the FP64 CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -381,11 +382,84 @@ def cpu_baseline(sc, counts):
     dt = time.perf_counter() - t0
     lattice = int(sum(counts["sobel3d"][i, 0] for i in views))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one thread on every sixteenth row of view 0; lattice samples from the
+    # oracle's own last lattice index per ray
+    cam = sc.cameras[0]
+    pix = np.concatenate([np.arange(r * cam["width"], (r + 1) * cam["width"])
+                          for r in range(0, cam["height"], 16)])
+    t0 = time.perf_counter()
+    r1 = oracle.render(v, cam, sc.tf, sc.shading, opt, pixels=pix, threads=1)
+    dt1 = time.perf_counter() - t0
+    hit = (r1["flags"] & oracle.FLAG_HIT) != 0
+    lattice1 = int((r1["k_last"][hit].astype(np.int64) + 1).sum())
     return {"value": round(lattice / dt / 1e9, 6), "unit": "Gsamples/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{len(views)} full 1024x1024 Sobel3D views (every sixth view of the "
                       f"orbit) of the 512^3 u16 workload: {lattice} lattice samples in "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "single_thread_value": round(lattice1 / dt1 / 1e9, 6),
+            "single_thread_sample": f"every 16th row of view 0, one thread: {lattice1} lattice "
+                                    f"samples in {dt1:.1f} s"}
+
+
+def measured_peaks():
+    """Rates this GPU reaches on plain probes (``libpeaks.so``), beside the
+    datasheet peaks: FP32 FMA built like the raycaster (no packed FP32), reads
+    of a 2 MiB buffer that stays in each XCD's L2, reads of a 1 GiB buffer
+    (HBM), and a 1 GiB device copy (read + write).  Best of five each."""
+    path = os.path.join(ROOT, "paper_1609_01317_amd", "libpeaks.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    lib.pk_fma.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    lib.pk_read.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_void_p, ctypes.c_void_p]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def best_ms(fn, n=5):
+        fn()
+        ts = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return min(ts)
+
+    def check(rc_):
+        if rc_ != 0:
+            raise RuntimeError(f"peak probe failed with HIP error {rc_}")
+
+    fma_blocks, fma_iters = 4096, 2048
+    out = torch.empty(fma_blocks * 256, dtype=torch.float32, device="cuda")
+    ms = best_ms(lambda: check(lib.pk_fma(out.data_ptr(), fma_blocks, fma_iters, stream)))
+    fma_tflops = 2 * 16 * fma_iters * fma_blocks * 256 / (ms * 1e-3) / 1e12
+
+    rd_blocks = 2048
+    out = torch.empty(rd_blocks * 256, dtype=torch.float32, device="cuda")
+    rates = {}
+    # 2 MiB: 512 chunks of 4 KiB, inside each XCD's 4 MB L2; 1 GiB: 262144
+    # chunks, two passes over it (2048 workgroups x 256 repetitions)
+    for name, nbytes, reps in (("l2", 2 << 20, 512), ("hbm", 1 << 30, 256)):
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        ms = best_ms(lambda: check(lib.pk_read(buf.data_ptr(), nbytes, rd_blocks, reps,
+                                               out.data_ptr(), stream)))
+        rates[name] = rd_blocks * reps * 4096 / (ms * 1e-3) / 1e12
+        del buf
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ms = best_ms(lambda: b.copy_(a))
+    copy_tbs = 2 * a.numel() * 4 / (ms * 1e-3) / 1e12
+    del a, b
+    return {"fp32_fma_tflops": round(fma_tflops, 2), "l2_read_tb_s": round(rates["l2"], 2),
+            "hbm_read_tb_s": round(rates["hbm"], 2), "hbm_copy_tb_s": round(copy_tbs, 2),
+            "probe": "FP32 FMA: 16 independent chains x 2048 steps per lane, 4096 x 256 lanes, "
+                     "no packed FP32; reads: 2048 workgroups each reading one 4 KiB chunk per "
+                     "repetition, walking a 2 MiB (L2, 512 repetitions) or 1 GiB (HBM, two "
+                     "passes) buffer; copy: 1 GiB float32, read + write "
+                     "bytes"}
 
 
 def calib_copy():
@@ -450,6 +524,10 @@ def main():
                       "chunks_direct": int(counts[op][:, 6].sum()),
                       "samples_direct": int(counts[op][:, 7].sum())}
     roof = roofline(render_ms, counts)
+    log("bench: measured peaks")
+    peaks = measured_peaks()
+    roof["measured_peaks"] = peaks
+    roof["frac_of_measured_fp32_fma"] = round(roof["achieved"] / peaks["fp32_fma_tflops"], 4)
     result = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),

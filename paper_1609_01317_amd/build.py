@@ -1,7 +1,8 @@
 """Build ``librc.so`` (the HIP/gfx950 raycaster) in-tree with hipcc.
 
 Each ``csrc/*.hip`` file is compiled to an object in parallel, then the
-objects are linked into ``paper_1609_01317_amd/librc.so``.
+objects are linked into ``paper_1609_01317_amd/librc.so``.  The benchmark's
+peak-rate probes (``peaks/peaks.hip``) become ``libpeaks.so`` beside it.
 """
 from __future__ import annotations
 
@@ -15,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librc.so")
+PEAKS = os.path.join(HERE, "libpeaks.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -55,6 +57,15 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)
+    # the benchmark's peak-rate probes: a library of their own
+    src = os.path.join(HERE, "peaks", "peaks.hip")
+    tmp = PEAKS + ".tmp"
+    r = subprocess.run([HIPCC, *FLAGS, "-shared", "-o", tmp, src], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PEAKS)
+    if verbose:
+        print("built", PEAKS)
     return OUT
 
 

@@ -216,12 +216,19 @@ def _views_scene(n_views, seed=61, image=(40, 36)):
     return sc, cams
 
 
-def test_render_views_equals_single_renders():
-    """20 views (two launches of at most 16), mixed image sizes, skipping on."""
-    sc = W.config_small(seed=62, dims=(30, 26, 22), dtype=np.uint16, image=(37, 29),
-                        op="sobel3d", ert=0.95, skip=True)
-    cams = [W.orbit_camera((30, 26, 22), sc.spacing, 18.0 * i, 30.0 - 4 * i, 24 + 8 * (i % 3),
-                           16 + 8 * (i % 4)) for i in range(20)]
+@pytest.mark.parametrize("seed,dtype,op,shading,n_views,skip",
+                         [(62, np.uint16, "sobel3d", "blinn_phong", 20, True),
+                          (64, np.uint8, "central", "paper_lambert", 33, False),
+                          (65, np.float32, "zucker_hummel", "none", 17, True),
+                          (66, np.float32, "central", "blinn_phong", 1, True)])
+def test_render_views_equals_single_renders(seed, dtype, op, shading, n_views, skip):
+    """Views in launches of at most 16 (the item scratch reused across
+    launches), mixed image sizes, every box budget and the unshaded kinds:
+    bit-identical to one rc_render per view, aux included."""
+    sc = W.config_small(seed=seed, dims=(30, 26, 22), dtype=dtype, image=(37, 29), op=op,
+                        shading=shading, ert=0.95, skip=skip)
+    cams = [W.orbit_camera((30, 26, 22), sc.spacing, 18.0 * i, 30.0 - 4 * (i % 15), 24 + 8 * (i % 3),
+                           16 + 8 * (i % 4)) for i in range(n_views)]
     vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
     rc.rc_build_bricks(vol, 8)
     tf = to_dev(sc.tf)
