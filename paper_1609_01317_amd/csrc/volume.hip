@@ -22,6 +22,10 @@ rc_status fail(rc_status st, const char* fmt, ...) {
 }
 
 rc_status hip_fail(hipError_t e, const char* what) {
+    // the error is reported here: clear the runtime's last-error state so a
+    // later launch check does not see it again (after a failed allocation
+    // the library stays usable)
+    (void)hipGetLastError();
     if (e == hipErrorOutOfMemory)
         return fail(RC_E_OOM, "%s: %s", what, hipGetErrorString(e));
     return fail(RC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
