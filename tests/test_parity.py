@@ -242,6 +242,32 @@ def test_empty_clip_box_gives_black():
     assert np.all(g["rgba"] == 0)
 
 
+def test_allocation_failure_is_rc_e_oom():
+    """A host-forcible failure: with the device memory taken by other
+    allocations, rc_create_volume's bricked copy cannot be allocated and the
+    call returns RC_E_OOM without creating a volume (the largest accepted
+    volume, 2^31 voxels, is far smaller than the device, so only memory
+    pressure reaches this status)."""
+    src = torch.zeros((128, 512, 512), dtype=torch.float32, device="cuda")   # 128 MiB
+    hold = []
+    try:
+        for chunk in (16 << 30, 1 << 30, 64 << 20):
+            while True:
+                try:
+                    hold.append(torch.empty(chunk, dtype=torch.uint8, device="cuda"))
+                except torch.OutOfMemoryError:
+                    break
+        with pytest.raises(rc.RCError) as e:
+            rc.rc_create_volume(src, (1.0, 1.0, 1.0), 0.0, 1.0)
+        assert e.value.status == rc.RC_E_OOM, str(e.value)
+    finally:
+        del hold
+        torch.cuda.empty_cache()
+    # and the library works again once memory is free
+    vol = rc.rc_create_volume(src, (1.0, 1.0, 1.0), 0.0, 1.0)
+    del vol
+
+
 def test_error_statuses():
     sc = W.config_small(seed=20, dims=(12, 12, 12), image=(8, 8))
     vol = gpu_volume(sc, bricks=False)
