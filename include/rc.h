@@ -344,6 +344,19 @@ void rc_destroy_volume(rc_volume* vol);
 /* Message for the last non-OK status returned on the calling thread. */
 const char* rc_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Bounds-checked build (librc_debug.so, compiled with RC_DEBUG_BOUNDS; for
+ * tests).  There every device-side index into a volume, brick mask, table,
+ * LDS box, image or gradient buffer is checked against its buffer; an index
+ * outside it is counted and replaced by 0, so the access stays inside the
+ * buffer and the run goes on.  One counter per device.
+ * rc_debug_bounds_violations synchronises the device and writes the count
+ * to *out (host pointer); rc_debug_bounds_reset sets it to 0.  In the
+ * product build (librc.so) both return RC_E_UNSUPPORTED.
+ * ---------------------------------------------------------------------- */
+rc_status rc_debug_bounds_violations(unsigned long long* out);
+rc_status rc_debug_bounds_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,11 +20,16 @@ __all__ = [
     "camera_struct", "shading_struct", "options_struct", "library_path",
     "Batch", "rc_batch_create", "rc_batch_render", "rc_batch_destroy", "rc_render_batch",
     "rc_batch_autotune", "rc_render_views", "rc_render_backward_views", "RenderViewsFn",
-    "rc_render_surface", "surface_options_struct",
+    "rc_render_surface", "surface_options_struct", "rc_debug_bounds_violations",
+    "rc_debug_bounds_reset",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "librc.so")
+# RC_LIBRARY=debug selects the bounds-checked build (librc_debug.so), for tests
+_LIB_NAMES = {"": "librc.so", "product": "librc.so", "debug": "librc_debug.so"}
+if os.environ.get("RC_LIBRARY", "") not in _LIB_NAMES:
+    raise RuntimeError(f"RC_LIBRARY must be one of {sorted(_LIB_NAMES)[1:]}")
+_LIB_PATH = os.path.join(_HERE, _LIB_NAMES[os.environ.get("RC_LIBRARY", "")])
 
 RC_OK, RC_E_INVALID, RC_E_OOM, RC_E_DEVICE, RC_E_STATE, RC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 RC_U8, RC_U16, RC_F32 = 0, 1, 2
@@ -149,6 +154,10 @@ def _L():
         L.rc_render_surface.argtypes = [vp, C.POINTER(rc_camera), vp, C.c_int,
                                         C.POINTER(rc_shading), C.POINTER(rc_surface_options), vp,
                                         vp, vp]
+        L.rc_debug_bounds_violations.restype = C.c_int
+        L.rc_debug_bounds_violations.argtypes = [C.POINTER(C.c_ulonglong)]
+        L.rc_debug_bounds_reset.restype = C.c_int
+        L.rc_debug_bounds_reset.argtypes = []
         _lib = L
     return _lib
 
@@ -160,6 +169,19 @@ def rc_last_error() -> str:
 def _check(st):
     if st != RC_OK:
         raise RCError(st, rc_last_error())
+
+
+def rc_debug_bounds_violations() -> int:
+    """Device-side index violations counted by the bounds-checked build since
+    the last reset (synchronises the device); RCError(RC_E_UNSUPPORTED) in
+    the product build."""
+    n = C.c_ulonglong(0)
+    _check(_L().rc_debug_bounds_violations(C.byref(n)))
+    return int(n.value)
+
+
+def rc_debug_bounds_reset():
+    _check(_L().rc_debug_bounds_reset())
 
 
 def _stream(stream):

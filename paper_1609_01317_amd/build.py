@@ -1,7 +1,9 @@
 """Build ``librc.so`` (the HIP/gfx950 raycaster) in-tree with hipcc.
 
 Each ``csrc/*.hip`` file is compiled to an object in parallel, then the
-objects are linked into ``paper_1609_01317_amd/librc.so``.  The benchmark's
+objects are linked into ``paper_1609_01317_amd/librc.so``; the same sources
+built with ``-DRC_DEBUG_BOUNDS`` (device-side index checks) become
+``librc_debug.so``.  The benchmark's
 peak-rate probes (``peaks/peaks.hip``) become ``libpeaks.so`` beside it.
 """
 from __future__ import annotations
@@ -17,6 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librc.so")
 PEAKS = os.path.join(HERE, "libpeaks.so")
+DEBUG = os.path.join(HERE, "librc_debug.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -35,28 +38,38 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(job) -> str:
+    src, tag, extra = job
+    obj = os.path.join(BUILD, tag, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = OUT + ".tmp"
+def _link(objs, out):
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, OUT)
-    if verbose:
-        print("built", OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # the product library and the bounds-checked build of the same sources
+    variants = (("product", [], OUT), ("debug", ["-DRC_DEBUG_BOUNDS"], DEBUG))
+    for tag, _, _ in variants:
+        os.makedirs(os.path.join(BUILD, tag), exist_ok=True)
+    jobs = [(s, tag, extra) for tag, extra, _ in variants for s in srcs]
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        objs = list(ex.map(_compile, jobs))
+    for k, (tag, _, out) in enumerate(variants):
+        _link(objs[k * len(srcs):(k + 1) * len(srcs)], out)
+        if verbose:
+            print("built", out)
     # the benchmark's peak-rate probes: a library of their own
     src = os.path.join(HERE, "peaks", "peaks.hip")
     tmp = PEAKS + ".tmp"

@@ -25,7 +25,8 @@ __global__ __launch_bounds__(64) void raycast_adaptive(RenderParams P) {
     if (valid) setup_ray(P, V, px, py, R);
     RayShade rs;
     ray_shade(P, R, rs);
-    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
+    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
+                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
     const double big_step = (double)P.adapt * P.step;
     float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.0f;
     int j = 0, last = -1;
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(64) void raycast_adaptive(RenderParams P) {
             const bool poor = (double)r.y - (double)r.x <= (double)P.adapt_range;
             const double step = poor ? big_step : P.step;
             last = j;
-            if (!(P.skip && P.empty[b])) {
+            if (!(P.skip && P.empty[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)])) {
                 ++evaluated;
                 int ox[4], oy[4], oz[4];
                 src.offsets(C, ox, oy, oz);
@@ -75,8 +76,8 @@ __global__ __launch_bounds__(64) void raycast_adaptive(RenderParams P) {
     }
     if (valid) {
         long long pix = (long long)py * V.W + px;
-        V.out[pix] = make_float4(Cr, Cg, Cb, 1.0f - T);
-        if (V.aux) V.aux[pix] = rc_aux{(int)last, T};
+        V.out[RC_IDX(P.dbg, pix, (long long)V.W * V.H)] = make_float4(Cr, Cg, Cb, 1.0f - T);
+        if (V.aux) V.aux[RC_IDX(P.dbg, pix, (long long)V.W * V.H)] = rc_aux{(int)last, T};
     }
     if (P.stats) {
         unsigned lat = wave_sum(valid ? (unsigned)(last + 1) : 0u);

@@ -15,6 +15,8 @@ struct BackwardParams {
     float* dtf;             // [M][4]
     int lds_tf;             // 1: accumulate the table gradient in LDS first
     int lds_table;          // 1: read the table from an LDS copy
+    int M4;                 // table entries * 4 (the dTF length)
+    unsigned int* dbg;      // bounds-checked build: violation counter; else null
 };
 
 constexpr int kBwdTile = 8;               // 8x8 pixels, one wave per workgroup
@@ -24,8 +26,8 @@ constexpr float kTinyT = 1e-30f;
 
 __device__ __forceinline__ void add_dtf(const BackwardParams& B, float* lds, int i, int ch, float v) {
     if (v == 0.0f) return;
-    if (B.lds_tf) atomicAdd(&lds[i * 4 + ch], v);
-    else unsafeAtomicAdd(&B.dtf[i * 4 + ch], v);
+    if (B.lds_tf) atomicAdd(&lds[RC_IDX(B.dbg, i * 4 + ch, B.M4)], v);
+    else unsafeAtomicAdd(&B.dtf[RC_IDX(B.dbg, i * 4 + ch, B.M4)], v);
 }
 
 // A ray's table-gradient contributions, summed in registers while its
@@ -92,7 +94,8 @@ template <typename VT>
 __device__ __forceinline__ void bwd_fetch(const RenderParams& P, const Ray& R, int k,
                                           BwdSample& S, float corner[8]) {
     lattice_point(P, R, k, S.C, S.pv);
-    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
+    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
+                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
     src.offsets(S.C, S.ox, S.oy, S.oz);
     load_corners<VT>(src.base, S.ox, S.oy, S.oz, corner);
 }
@@ -108,8 +111,8 @@ __device__ __forceinline__ void bwd_finish(const RenderParams& P, const float4* 
     S.i = min((int)uu, P.M - 1);
     S.i1 = min(S.i + 1, P.M - 1);
     S.t = uu - (float)S.i;
-    S.e0 = tab[S.i];
-    S.e1 = tab[S.i1];
+    S.e0 = tab[RC_IDX(P.dbg, S.i, P.M)];
+    S.e1 = tab[RC_IDX(P.dbg, S.i1, P.M)];
     S.rgba = make_float4(lerpf(S.e0.x, S.e1.x, S.t), lerpf(S.e0.y, S.e1.y, S.t),
                          lerpf(S.e0.z, S.e1.z, S.t), lerpf(S.e0.w, S.e1.w, S.t));
     S.a = S.rgba.w;
@@ -156,7 +159,9 @@ __device__ __forceinline__ void dv_flush(const RenderParams& P, const BackwardPa
         int x = clampi(r.c[0] + (q & 1), 0, P.nx - 1);
         int y = clampi(r.c[1] + ((q >> 1) & 1), 0, P.ny - 1);
         int z = clampi(r.c[2] + (q >> 2), 0, P.nz - 1);
-        unsafeAtomicAdd(&B.dvol[((long long)z * P.ny + y) * P.nx + x], r.w[q]);
+        unsafeAtomicAdd(&B.dvol[RC_IDX(P.dbg, ((long long)z * P.ny + y) * P.nx + x,
+                                       (long long)P.nx * P.ny * P.nz)],
+                        r.w[q]);
     }
     r.c[0] = INT_MIN;
 }
@@ -271,7 +276,10 @@ __device__ __forceinline__ void gradient_adjoint(const RenderParams& P, const Ba
                 float w = gx * kx.D[x] * (fxA + fxL);
                 w = fmaf(gy, fmaf(kx.A[x], fyA, kx.L[x] * fyL), w);
                 w = fmaf(gz, fmaf(kx.A[x], fzA, kx.L[x] * fzL), w);
-                if (w != 0.0f) unsafeAtomicAdd(&Bp.dvol[row + xi[x]], w);
+                if (w != 0.0f)
+                    unsafeAtomicAdd(&Bp.dvol[RC_IDX(P.dbg, row + xi[x],
+                                                    (long long)P.nx * P.ny * P.nz)],
+                                    w);
             }
         }
 }
@@ -343,8 +351,8 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
         RayShade rs;
         ray_shade(P, R, rs);
         long long pix = (long long)py * V.W + px;
-        rc_aux ax = V.aux[pix];
-        float4 g = V.grad[pix];
+        rc_aux ax = V.aux[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
+        float4 g = V.grad[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
         int last = ax.k_last;
         if (R.K >= 0 && last >= 0 && last <= R.K) {
             // Anchor: the last index a whose front transmittance T_a is at
@@ -450,6 +458,8 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
     Bp.dtf = grad_tf_dev;
     Bp.lds_tf = tf_len <= kBwdLdsEntries;
     Bp.lds_table = tf_len <= kBwdLdsTable;
+    Bp.M4 = tf_len * 4;
+    Bp.dbg = P.dbg;
     size_t lds = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 4 * sizeof(float);
     for (int first = 0; first < n_views; first += kMaxViews) {
         ViewSet S;

@@ -148,6 +148,21 @@ __host__ __device__ inline int view_of_unit(const ViewSet& S, int unit, int j, i
     return -1;
 }
 
+// ---------------------------------------------------------------- index checks
+// In the bounds-checked build (RC_DEBUG_BOUNDS) an index outside [0, n) is
+// counted in P.dbg and replaced by 0, so the access stays inside its buffer
+// and the run continues; in the product build the index passes unchanged.
+#ifdef RC_DEBUG_BOUNDS
+__device__ __forceinline__ long long rc_checked(unsigned int* dbg, long long i, long long n) {
+    if (i >= 0 && i < n) return i;
+    if (dbg) atomicAdd(dbg, 1u);
+    return 0;
+}
+#define RC_IDX(dbg, i, n) rc_checked((dbg), (i), (n))
+#else
+#define RC_IDX(dbg, i, n) (i)
+#endif
+
 // ---------------------------------------------------------------- ray set-up
 // Camera ray through the centre of pixel (px, py) and its span inside the
 // sampling box (Section 3.3: no intersection -> black; two -> sample between).
@@ -256,6 +271,8 @@ struct GlobalSrc {
     using elem = VT;
     const VT* __restrict__ base;
     int nx, ny, nz, sy, sz;
+    long long n;            // elements of the bricked volume
+    unsigned int* dbg;
     __device__ __forceinline__ void offsets(const Cell& C, int ox[4], int oy[4], int oz[4]) const {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -263,6 +280,18 @@ struct GlobalSrc {
             oy[i] = off_y(clampi(C.c[1] - 1 + i, 0, ny - 1), sy);
             oz[i] = off_z(clampi(C.c[2] - 1 + i, 0, nz - 1), sz);
         }
+#ifdef RC_DEBUG_BOUNDS
+        // the separable terms are non-negative: the footprint's largest
+        // offset is the sum of the per-axis largest
+        int mx = 0, my = 0, mz = 0, lx = ox[0], ly = oy[0], lz = oz[0];
+        for (int i = 0; i < 4; ++i) {
+            mx = max(mx, ox[i]); my = max(my, oy[i]); mz = max(mz, oz[i]);
+            lx = min(lx, ox[i]); ly = min(ly, oy[i]); lz = min(lz, oz[i]);
+        }
+        if (RC_IDX(dbg, (long long)lx + ly + lz, n) != (long long)lx + ly + lz ||
+            RC_IDX(dbg, (long long)mx + my + mz, n) != (long long)mx + my + mz)
+            for (int i = 0; i < 4; ++i) ox[i] = oy[i] = oz[i] = 0;
+#endif
     }
 };
 
@@ -272,6 +301,8 @@ struct LdsSrc {
     const VT* base;
     int lo[3];          // box origin (voxel index, may be negative)
     int bx, bxy;        // row and slab strides in elements
+    int n;              // elements of the staged box
+    unsigned int* dbg;
     __device__ __forceinline__ void offsets(const Cell& C, int ox[4], int oy[4], int oz[4]) const {
         int x0 = C.c[0] - 1 - lo[0], y0 = C.c[1] - 1 - lo[1], z0 = C.c[2] - 1 - lo[2];
         // box coordinates and strides are far below 2^23: 24-bit multiplies
@@ -282,6 +313,18 @@ struct LdsSrc {
             oy[i] = yb + i * bx;
             oz[i] = zb + i * bxy;
         }
+#ifdef RC_DEBUG_BOUNDS
+        // offsets grow with i on every axis: check the two extreme corners
+        // and every per-axis coordinate against the box
+        const int zd = n / bxy, yd = bxy / bx;
+        const bool bad = x0 < 0 || x0 + 3 >= bx || y0 < 0 || y0 + 3 >= yd || z0 < 0 ||
+                         z0 + 3 >= zd;
+        if (bad || RC_IDX(dbg, (long long)ox[0] + oy[0] + oz[0], n) != ox[0] + oy[0] + oz[0] ||
+            RC_IDX(dbg, (long long)ox[3] + oy[3] + oz[3], n) != ox[3] + oy[3] + oz[3]) {
+            if (bad && dbg) atomicAdd(dbg, 1u);
+            for (int i = 0; i < 4; ++i) ox[i] = oy[i] = oz[i] = 0;
+        }
+#endif
     }
 };
 
@@ -331,7 +374,7 @@ __device__ __forceinline__ float4 tf_lookup(const RenderParams& P, float v) {
     int i = min((int)uu, P.M - 1);
     int i1 = min(i + 1, P.M - 1);
     float t = uu - (float)i;
-    float4 a = P.tf[i], b = P.tf[i1];
+    float4 a = P.tf[RC_IDX(P.dbg, i, P.M)], b = P.tf[RC_IDX(P.dbg, i1, P.M)];
     return make_float4(lerpf(a.x, b.x, t), lerpf(a.y, b.y, t), lerpf(a.z, b.z, t),
                        lerpf(a.w, b.w, t));
 }
@@ -600,6 +643,13 @@ __device__ inline void stage_box(const RenderParams& P, LT* lds, const int lo[3]
         for (int iz = 0; iz < gz; ++iz, l0 += 2 * bxy) {
             int z0 = lo[2] + 2 * iz;
             if (xy_in && z0 >= 0 && z0 + 1 < zmax) {
+#ifdef RC_DEBUG_BOUNDS
+                // the group's 8 voxels and its 4 pair stores
+                if (RC_IDX(P.dbg, (long long)oxy + off_z(z0, P.sz) + 7,
+                           (long long)P.nbx * P.nby * P.nbz * 512) == 0 ||
+                    RC_IDX(P.dbg, l0 + bxy + bx + 1, bxy * dim[2]) == 0)
+                    continue;
+#endif
                 const G* src = (const G*)(vox + oxy + off_z(z0, P.sz));
                 // l0 and the strides are even: pair-aligned stores
                 if constexpr (std::is_same<LT, float>::value) {
@@ -623,8 +673,9 @@ __device__ inline void stage_box(const RenderParams& P, LT* lds, const int lo[3]
                     int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
                     int x = clampi(x0 + dx, 0, P.nx - 1), y = clampi(y0 + dy, 0, P.ny - 1),
                         z = clampi(z0 + dz, 0, P.nz - 1);
-                    lds[l0 + dz * bxy + dy * bx + dx] =
-                        (LT)vox[off_x(x) + off_y(y, P.sy) + off_z(z, P.sz)];
+                    lds[RC_IDX(P.dbg, l0 + dz * bxy + dy * bx + dx, bxy * dim[2])] =
+                        (LT)vox[RC_IDX(P.dbg, off_x(x) + off_y(y, P.sy) + off_z(z, P.sz),
+                                       (long long)P.nbx * P.nby * P.nbz * 512)];
                 }
             }
         }
@@ -722,7 +773,8 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
                 r1 < ch.bdim[1] && r2 < ch.bdim[2])
                 empty = ((ch.live >> ((r2 * ch.bdim[1] + r1) * ch.bdim[0] + r0)) & 1ull) == 0;
             else
-                empty = P.empty[(b2 * P.nby + b1) * P.nbx + b0] != 0;
+                empty = P.empty[RC_IDX(P.dbg, (b2 * P.nby + b1) * P.nbx + b0,
+                                       (long long)P.nbx * P.nby * P.nbz)] != 0;
             if (empty) continue;
         }
         ++S.evaluated;
@@ -806,7 +858,9 @@ __device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const R
         bool live = false;
         if (lane < nsr) {
             int r0 = lane % sdim[0], r1 = (lane / sdim[0]) % sdim[1], r2 = lane / (sdim[0] * sdim[1]);
-            live = P.super_empty[((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0] == 0;
+            live = P.super_empty[RC_IDX(P.dbg,
+                                        ((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0,
+                                        (long long)P.nsx * P.nsy * P.nsz)] == 0;
         }
         return __ballot(live) == 0ull;
     }
@@ -838,7 +892,9 @@ __device__ __forceinline__ int entry_index(const RenderParams& P, const Ray& R) 
     const float kmax = (float)R.K;
 #pragma unroll 1
     for (int it = 0; it < ns[0] + ns[1] + ns[2]; ++it) {
-        if (P.super_empty[(cell[2] * P.nsy + cell[1]) * P.nsx + cell[0]] == 0) break;
+        if (P.super_empty[RC_IDX(P.dbg, (cell[2] * P.nsy + cell[1]) * P.nsx + cell[0],
+                                 (long long)P.nsx * P.nsy * P.nsz)] == 0)
+            break;
         int a = kb[0] <= kb[1] ? (kb[0] <= kb[2] ? 0 : 2) : (kb[1] <= kb[2] ? 1 : 2);
         k_enter = kb[a];
         cell[a] += dir[a];
@@ -869,7 +925,8 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
     const bool stage = LIT;
     RayShade rs;
     ray_shade(P, R, rs);
-    const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
+    const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
+                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
     using LT = typename LdsT<VT, OP>::type;
     LT* lds = (LT*)lds_raw;
     const int cap = lds_bytes / (int)sizeof(LT);
@@ -936,7 +993,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
                 int r0 = lane % ch.bdim[0], r1 = (lane / ch.bdim[0]) % ch.bdim[1],
                     r2 = lane / (ch.bdim[0] * ch.bdim[1]);
                 int b = ((ch.blo[2] + r2) * P.nby + ch.blo[1] + r1) * P.nbx + ch.blo[0] + r0;
-                live = P.empty[b] == 0;
+                live = P.empty[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)] == 0;
             }
             ch.live = __ballot(live);
             ch.mixed = ch.live != (nbr == 64 ? ~0ull : ((1ull << nbr) - 1ull));
@@ -955,7 +1012,8 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
         } else {
             ++n_direct;
         }
-        LdsSrc<LT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1]};
+        LdsSrc<LT> lsrc{lds, {ch.lo[0], ch.lo[1], ch.lo[2]}, ch.dim[0], ch.dim[0] * ch.dim[1],
+                        ch.dim[0] * ch.dim[1] * ch.dim[2], P.dbg};
         if (active && kstop >= S.k)
             run_samples<VT, OP, LIT>(P, R, lsrc, gsrc, fits, ch, kstop, rs, S);
         if (fits) wave_lds_sync();
@@ -992,8 +1050,8 @@ __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, i
     march_wave<VT, OP, LIT>(P, R, valid, lds, lds_bytes, lane, M);
     if (valid) {
         long long pix = (long long)py * V.W + px;
-        V.out[pix] = M.rgba;
-        if (V.aux) V.aux[pix] = rc_aux{M.k_last, M.T};
+        V.out[RC_IDX(P.dbg, pix, (long long)V.W * V.H)] = M.rgba;
+        if (V.aux) V.aux[RC_IDX(P.dbg, pix, (long long)V.W * V.H)] = rc_aux{M.k_last, M.T};
     }
     if (P.stats) {
         unsigned lat = wave_sum(R.K >= 0 ? (unsigned)(M.k_last + 1) : 0u);

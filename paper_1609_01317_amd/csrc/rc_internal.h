@@ -113,6 +113,7 @@ struct RenderParams {
     const uint8_t* super_empty; // per-super-brick flag (4x4x4 bricks), or null
     int nsx, nsy, nsz;          // super-bricks per axis
     rc_stats* stats;            // kStatSlots consecutive copies, or null
+    unsigned int* dbg;          // bounds-checked build: violation counter; else null
 };
 
 // Several images of one volume in one launch (kernel-argument block).
@@ -142,6 +143,9 @@ size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
                           size_t* super_bytes);
 void set_tiling(ViewParams& V, int tile_w);     // tile_w in {4, 8, 16, 32, 64}
 void fill_view(ViewParams& V, const rc_camera* cam);
+// the bounds-checked build's violation counter on the current device (null
+// in the product build)
+unsigned int* debug_counter();
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
 // The persistent batched kernel over n items already in device memory
 // (queue reset included); total = the items' tiles, kinds/order as in

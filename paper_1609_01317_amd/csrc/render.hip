@@ -329,6 +329,56 @@ static double op_gain(int op) {
     return 2.0 * s;
 }
 
+// ---------------------------------------------------------------- bounds-checked build
+// One violation counter per device, allocated on first use; null in the
+// product build.
+#ifdef RC_DEBUG_BOUNDS
+static unsigned int* g_dbg[64] = {nullptr};
+#endif
+unsigned int* debug_counter() {
+#ifdef RC_DEBUG_BOUNDS
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (!g_dbg[dev]) {
+        unsigned int* p = nullptr;
+        if (hipMalloc(&p, sizeof(unsigned int)) != hipSuccess) return nullptr;
+        if (hipMemset(p, 0, sizeof(unsigned int)) != hipSuccess) return nullptr;
+        g_dbg[dev] = p;
+    }
+    return g_dbg[dev];
+#else
+    return nullptr;
+#endif
+}
+
+extern "C" rc_status rc_debug_bounds_violations(unsigned long long* out) {
+    if (!out) return fail(RC_E_INVALID, "rc_debug_bounds_violations: out is NULL");
+#ifdef RC_DEBUG_BOUNDS
+    unsigned int* p = debug_counter();
+    if (!p) return fail(RC_E_DEVICE, "rc_debug_bounds_violations: no counter on this device");
+    unsigned int h = 0;
+    RC_HIP(hipDeviceSynchronize());
+    RC_HIP(hipMemcpy(&h, p, sizeof h, hipMemcpyDeviceToHost));
+    *out = h;
+    return RC_OK;
+#else
+    return fail(RC_E_UNSUPPORTED, "rc_debug_bounds_violations: built without bounds checks");
+#endif
+}
+
+extern "C" rc_status rc_debug_bounds_reset(void) {
+#ifdef RC_DEBUG_BOUNDS
+    unsigned int* p = debug_counter();
+    if (!p) return fail(RC_E_DEVICE, "rc_debug_bounds_reset: no counter on this device");
+    RC_HIP(hipDeviceSynchronize());
+    RC_HIP(hipMemset(p, 0, sizeof(unsigned int)));
+    RC_HIP(hipDeviceSynchronize());
+    return RC_OK;
+#else
+    return fail(RC_E_UNSUPPORTED, "rc_debug_bounds_reset: built without bounds checks");
+#endif
+}
+
 void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* cam,
                         const float* tf, int tf_len, const rc_shading* sh, const rc_options* opt) {
     fill_view(P.view, cam);
@@ -384,6 +434,7 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     P.nsy = v->nsy;
     P.nsz = v->nsz;
     P.stats = nullptr;
+    P.dbg = debug_counter();
 }
 
 }  // namespace rc

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(64) void raycast_surface(RenderParams P, SurfacePar
     if (px >= V.W || py >= V.H) return;
     Ray R;
     setup_ray(P, V, px, py, R);
-    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz};
+    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
+                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
     Cell C;
     double pv[3];
     // coarse march: the first lattice sample inside the window
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(64) void raycast_surface(RenderParams P, SurfacePar
         t_hit = (float)t;
     }
     long long pix = (long long)py * V.W + px;
-    V.out[pix] = out;
+    V.out[RC_IDX(P.dbg, pix, (long long)V.W * V.H)] = out;
     if (S.t_hit) S.t_hit[pix] = t_hit;
 }
 
