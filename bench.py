@@ -16,8 +16,10 @@ operator are checked bit for bit against it.
 
 Also reported (outside `value`): per-operator rates and frame rates, the
 differentiable form (16 views of a 128^3 f32 volume, forward and
-forward+backward against the plain forward), the dominant kernel's
-roofline position, and the FP64 CPU oracle timed on a bounded sample.
+forward+backward against the plain forward), the batched form (64 uneven
+volumes), the first-hit surface form, the dominant kernel's roofline
+position beside peaks measured on this GPU by plain probes, and the FP64
+CPU oracle timed on a bounded sample (all threads, and one thread).
 """
 from __future__ import annotations
 
