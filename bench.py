@@ -7,9 +7,9 @@ step 0.5, early ray termination at 0.99 and 8^3-brick empty-space skipping.
 
 One step = the whole hot path over that input: re-ingest the resident
 linear volume into the brick layout, rebuild the brick value ranges, then
-render the 108 views (36 views x 3 operators): each operator's orbit is a
-render list built once before timing and rendered in one persistent
-batched launch per step, with its empty-brick masks recomputed.  `value` =
+render the 108 views (36 views x 3 operators): one render list built once
+before timing and rendered in one persistent batched launch per step, with
+its empty-brick masks recomputed.  `value` =
 lattice samples of one step / step time (Gsamples/s).  The single-image
 path (one rc_render per view) is timed beside it, and two views per
 operator are checked bit for bit against it.
@@ -74,16 +74,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch of raycast_batch (mean over the orbit launches of
-    the three operators) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary, or None when the kernel sources changed since the counters were
-    taken."""
+def recorded_traffic(views_per_launch):
+    """HBM bytes per launch of raycast_batch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
+    since the counters were taken or the summary's launches rendered a
+    different number of views."""
     if not os.path.exists(PROFILE):
         return None
     text = open(PROFILE).read()
     m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
     if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(r"views_per_launch:\s*(\d+)", text)
+    if not m or int(m.group(1)) != views_per_launch:
         return None
     m = re.search(r"hbm_bytes_per_launch\s+raycast_batch:\s*([0-9.eE+]+)", text)
     return float(m.group(1)) if m else None
@@ -111,11 +114,12 @@ def timed_pass(fn):
 
 
 def run_c3(args):
-    """The orbit of each operator is one render list of its views (an rc_batch
-    built once, before timing: cameras, outputs and options are fixed); a
-    step re-ingests the volume, rebuilds the brick ranges and renders the
-    three lists, each in one persistent launch (empty masks recomputed per
-    render, as rc_render does)."""
+    """The 108 views (36 per operator) are one render list (an rc_batch built
+    once, before timing: cameras, outputs and options are fixed; view i of
+    the three operators next to each other); a step re-ingests the volume,
+    rebuilds the brick ranges and renders the list in one persistent launch
+    (empty masks recomputed per render, as rc_render does).  Each operator's
+    orbit is also timed as a launch of its own, outside the step."""
     sc = W.config_c3(n_views=args.views)
     log(f"bench: c3 volume {sc.volume.shape} {sc.volume.dtype}, {len(sc.cameras)} views")
     src = to_dev(sc.volume)
@@ -132,22 +136,22 @@ def run_c3(args):
              for op in OPS}
     cache = os.path.join(ROOT, "_build", "batch_autotune.jsonl")
     os.makedirs(os.path.dirname(cache), exist_ok=True)
-    cfgs = {op: rc.rc_batch_autotune(items[op], cache) for op in OPS}
-    batches = {op: rc.rc_batch_create(items[op], cfgs[op]) for op in OPS}
+    all_items = [items[op][i] for i in range(len(sc.cameras)) for op in OPS]
+    cfg_all = rc.rc_batch_autotune(all_items, cache)
+    batch_all = rc.rc_batch_create(all_items, cfg_all)
 
     def step(events=None):
         rc.rc_update_volume(vol, src)
         rc.rc_build_bricks(vol, 8)
-        for op in OPS:
-            if events is None:
-                rc.rc_batch_render(batches[op])
-            else:
-                events[op].append(timed_pass(lambda: rc.rc_batch_render(batches[op])))
+        if events is None:
+            rc.rc_batch_render(batch_all)
+        else:
+            events.append(timed_pass(lambda: rc.rc_batch_render(batch_all)))
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    events = {op: [] for op in OPS}
+    events = []
     t0 = time.perf_counter()
     for s in range(args.steps):
         step(events)
@@ -155,7 +159,7 @@ def run_c3(args):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    render_ms = {op: [a.elapsed_time(b) for a, b in events[op]] for op in OPS}
+    render_ms = [a.elapsed_time(b) for a, b in events]
 
     # untimed: the single-image path (one rc_render per view), and the
     # counting pass (lattice / evaluated / shaded samples per view)
@@ -182,12 +186,24 @@ def run_c3(args):
             rc.rc_render(vol, sc.cameras[i], tf, sc.shading, opts[op], out=out)
             if not torch.equal(out, outs[op][i]):
                 raise RuntimeError(f"bench: batched {op} view {i} differs from rc_render")
-    return sc, vol, tf, ms_per_step, render_ms, single_ms, counts, cfgs
+    # untimed: each operator's orbit as a launch of its own
+    cfgs, op_ms = {"all": cfg_all}, {}
+    if not args.no_per_op:
+        for op in OPS:
+            cfgs[op] = rc.rc_batch_autotune(items[op], cache)
+            b = rc.rc_batch_create(items[op], cfgs[op])
+            rc.rc_batch_render(b)
+            ev = [timed_pass(lambda: rc.rc_batch_render(b)) for _ in range(2)]
+            torch.cuda.synchronize()
+            op_ms[op] = float(np.mean([x.elapsed_time(y) for x, y in ev]))
+            rc.rc_batch_destroy(b)
+    return sc, vol, tf, ms_per_step, render_ms, op_ms, single_ms, counts, cfgs
 
 
-def roofline(render_ms, counts):
-    """Dominant kernel: raycast_batch, one launch per operator's orbit; the
-    figures are per launch averaged over the three operators' launches."""
+def roofline(render_ms, counts, views_per_launch):
+    """Dominant kernel: raycast_batch, one launch per step rendering the 108
+    views of the three operators; the figures are per launch, averaged over
+    the timed steps."""
     flops_total = 0.0
     bytes_total = 0.0
     for op in OPS:
@@ -196,15 +212,15 @@ def roofline(render_ms, counts):
         flops_total += float((FLOPS_VALUE * (evaluated - shaded) + FLOPS_SHADED[op] * shaded).sum())
         bytes_total += float(
             2 * (VOXELS_VALUE * (evaluated - shaded) + VOXELS_SHADED[op] * shaded).sum())
-    launches = len(OPS)
-    avg_ms = float(np.mean([np.mean(render_ms[op]) for op in OPS]))
+    launches = 1
+    avg_ms = float(np.mean(render_ms))
     flops = flops_total / launches
     achieved = flops / (avg_ms * 1e-3) / 1e12
     return {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-        "traffic": recorded_traffic(),
-        "kernel": "raycast_batch (one launch = one operator's 36-view orbit)",
+        "traffic": recorded_traffic(views_per_launch),
+        "kernel": "raycast_batch (one launch = the 108 views of the three operators' orbits)",
         "avg_launch_ms": round(avg_ms, 4),
         "algorithmic_flops_per_launch": flops,
         "algorithmic_voxel_bytes_per_launch": bytes_total / launches,
@@ -485,6 +501,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the differentiable form")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB copy first")
+    ap.add_argument("--no-per-op", action="store_true",
+                    help="skip the per-operator orbit launches (profiling runs: every "
+                         "raycast_batch dispatch is then the step's)")
     ap.add_argument("--only", choices=["c4", "c5", "surface"], default=None,
                     help="run only the batched (c4), differentiable (c5) or first-hit surface "
                          "form and print it")
@@ -504,28 +523,30 @@ def main():
         print(json.dumps(fn(args)), flush=True)
         return
 
-    sc, vol, tf, ms_per_step, render_ms, single_ms, counts, cfgs = run_c3(args)
+    sc, vol, tf, ms_per_step, render_ms, op_ms, single_ms, counts, cfgs = run_c3(args)
     lattice_step = int(sum(counts[op][:, 0].sum() for op in OPS))
     value = lattice_step / (ms_per_step * 1e-3) / 1e9
     per_op = {}
     for op in OPS:
-        ms = float(np.sum(render_ms[op])) / args.steps
         lat = int(counts[op][:, 0].sum())
         ev = int(counts[op][:, 1].sum())
         ms1 = float(np.sum(single_ms[op]))
-        per_op[op] = {"orbit_ms": round(ms, 3), "fps": round(len(sc.cameras) / (ms * 1e-3), 1),
-                      "batch_config": cfgs[op],
-                      "single_image_orbit_ms": round(ms1, 3),
+        per_op[op] = {"single_image_orbit_ms": round(ms1, 3),
                       "single_image_ms_per_view": round(ms1 / len(sc.cameras), 4),
-                      "lattice_gsamples_s": round(lat / (ms * 1e-3) / 1e9, 3),
-                      "evaluated_gsamples_s": round(ev / (ms * 1e-3) / 1e9, 3),
                       "lattice_samples": lat, "evaluated_samples": ev,
                       "shaded_samples": int(counts[op][:, 2].sum()),
                       "chunks_staged": int(counts[op][:, 4].sum()),
                       "chunks_empty": int(counts[op][:, 5].sum()),
                       "chunks_direct": int(counts[op][:, 6].sum()),
                       "samples_direct": int(counts[op][:, 7].sum())}
-    roof = roofline(render_ms, counts)
+        if op in op_ms:         # the operator's orbit as a launch of its own
+            ms = op_ms[op]
+            per_op[op].update({"orbit_ms": round(ms, 3),
+                               "fps": round(len(sc.cameras) / (ms * 1e-3), 1),
+                               "batch_config": cfgs[op],
+                               "lattice_gsamples_s": round(lat / (ms * 1e-3) / 1e9, 3),
+                               "evaluated_gsamples_s": round(ev / (ms * 1e-3) / 1e9, 3)})
+    roof = roofline(render_ms, counts, len(OPS) * len(sc.cameras))
     log("bench: measured peaks")
     peaks = measured_peaks()
     roof["measured_peaks"] = peaks
@@ -539,10 +560,10 @@ def main():
                                "1024^2 perspective 60 deg, 36-view orbit at 10 deg steps x "
                                "{central difference, Sobel3D, Zucker-Hummel}, step 0.5, ERT 0.99, "
                                "8^3-brick skipping; step = ingest + brick ranges + the three "
-                               "operators' orbits, each one persistent batched launch of its 36 "
-                               "views",
+                               "operators' orbits (108 views) in one persistent batched launch",
                    "views": len(sc.cameras), "image": [1024, 1024], "volume": [512, 512, 512],
-                   "lattice_samples_per_step": lattice_step},
+                   "lattice_samples_per_step": lattice_step, "batch_config": cfgs["all"],
+                   "render_ms_per_step": round(float(np.mean(render_ms)), 3)},
         "per_operator": per_op,
         "roofline": roof,
     }
