@@ -23,6 +23,13 @@
  *    except the bricked copy a volume handle owns.  `stream` is a
  *    hipStream_t; NULL means the default stream.  All work is enqueued on
  *    that stream; calls return before it runs.
+ *  - Device memory the library allocates itself: a volume handle's bricked
+ *    copy and brick ranges (hipMalloc; freed by rc_destroy_volume), a
+ *    batch's descriptors, queue and masks (rc_batch_create; freed by
+ *    rc_batch_destroy), and the per-call scratch of rc_render and
+ *    rc_render_views (skip masks, counters, the views' item descriptors)
+ *    as stream-ordered allocations on `stream` (hipMallocAsync, released
+ *    with hipFreeAsync in the same call).
  *  - Errors: every argument is checked on the host before anything is
  *    enqueued, so a failing call leaves no partial work.  A call returns a
  *    negative rc_status and rc_last_error() describes it.  Nothing aborts
