@@ -44,7 +44,7 @@ import workloads as W  # noqa: E402
 OPS = ["central", "sobel3d", "zucker_hummel"]
 METRIC = "Gsamples/s fwd and fwd+bwd vs plain, 512³ vol→1024² img; % HBM/L2 roofline"
 
-# Algorithmic work per sample ("Roofline accounting"):
+# Algorithmic work per sample (the roofline's unit of work):
 # every evaluated sample pays the value path (8 voxels, trilinear + table
 # lookup); a sample with alpha != 0 additionally pays the gradient operator,
 # normalisation, shading and compositing.
