@@ -5,6 +5,7 @@
 // kernels; the
 // whole sequence can be captured into a HIP graph and replayed.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -375,18 +376,20 @@ static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
 rc_status rc::launch_batch_items(const RenderParams* items, const int* kinds, const int* tile_off,
                              const int* order, int n, int total, int* counter, int lds_bytes,
                              hipStream_t s) {
-    static int cus[64] = {0};
+    // compute units per device, looked up once (threads may race to store
+    // the same value)
+    static std::atomic<int> cus[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    if (cus[dev] == 0) {
-        int c = 0;
-        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            c < 1)
-            c = 256;
-        cus[dev] = c;
+    int n_cu = cus[dev].load(std::memory_order_relaxed);
+    if (n_cu == 0) {
+        if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n_cu < 1)
+            n_cu = 256;
+        cus[dev].store(n_cu, std::memory_order_relaxed);
     }
     hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL(raycast_batch, dim3((unsigned)(cus[dev] * 12)), dim3(64), (size_t)lds_bytes,
+    hipLaunchKernelGGL(raycast_batch, dim3((unsigned)(n_cu * 12)), dim3(64), (size_t)lds_bytes,
                        s, items, kinds, tile_off, order, n, total, counter, lds_bytes);
     RC_HIP(hipGetLastError());
     return RC_OK;

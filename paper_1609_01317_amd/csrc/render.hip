@@ -1,6 +1,7 @@
 // Forward render: argument checks, the per-render empty-brick mask and the
 // raycast kernel (one ray per pixel, Section 3.10).
 #include <cmath>
+#include <mutex>
 
 #include "march.h"
 
@@ -334,11 +335,13 @@ static double op_gain(int op) {
 // product build.
 #ifdef RC_DEBUG_BOUNDS
 static unsigned int* g_dbg[64] = {nullptr};
+static std::mutex g_dbg_lock;
 #endif
 unsigned int* debug_counter() {
 #ifdef RC_DEBUG_BOUNDS
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> guard(g_dbg_lock);
     if (!g_dbg[dev]) {
         unsigned int* p = nullptr;
         if (hipMalloc(&p, sizeof(unsigned int)) != hipSuccess) return nullptr;
