@@ -6,7 +6,8 @@ three gradient operators (central difference, Sobel3D, Zucker-Hummel),
 step 0.5, early ray termination at 0.99 and 8^3-brick empty-space skipping.
 
 One step = the whole hot path over that input: re-ingest the resident
-linear volume into the brick layout, rebuild the brick value ranges, then
+linear volume into the brick layout (which rebuilds the brick value
+ranges), then
 render the 108 views (36 views x 3 operators): one render list built once
 before timing and rendered in one persistent batched launch per step, with
 its empty-brick masks recomputed.  `value` =
@@ -16,8 +17,10 @@ operator are checked bit for bit against it.
 
 Also reported (outside `value`): per-operator rates and frame rates, the
 differentiable form (16 views of a 128^3 f32 volume, forward and
-forward+backward against the plain forward), the batched form (64 uneven
-volumes), the first-hit surface form, the dominant kernel's roofline
+forward+backward against the plain forward; and four 1024^2 views of the
+512^3 phantom with Sobel3D shading), the batched form (64 uneven
+volumes), the first-hit surface form, adaptive sampling on the orbit
+against the fixed step, the dominant kernel's roofline
 position beside peaks measured on this GPU by plain probes, and the FP64
 CPU oracle timed on a bounded sample (all threads, and one thread).
 """
@@ -113,6 +116,31 @@ def timed_pass(fn):
     return e0, e1
 
 
+AUTOTUNE_CACHE = os.path.join(ROOT, "_build", "batch_autotune.jsonl")
+
+
+def c3_render_list(sc, vol, tf):
+    """The headline render list: for each operator one item per orbit view
+    (its own output image), and ``all_items``, the 108 items in launch order
+    (view i of the three operators next to each other)."""
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    opts = {op: c3_options(sc, op) for op in OPS}
+    items = {op: [{"vol": vol, "camera": cam, "tf": tf, "shading": sc.shading,
+                   "options": opts[op],
+                   "out": torch.empty((H, Wd, 4), dtype=torch.float32, device="cuda")}
+                  for cam in sc.cameras] for op in OPS}
+    all_items = [items[op][i] for i in range(len(sc.cameras)) for op in OPS]
+    return items, all_items
+
+
+def c3_batch(all_items):
+    """The launch the step times: the autotuned configuration (cached as
+    JSON lines under _build/) and the batch built with it."""
+    os.makedirs(os.path.dirname(AUTOTUNE_CACHE), exist_ok=True)
+    cfg = rc.rc_batch_autotune(all_items, AUTOTUNE_CACHE)
+    return cfg, rc.rc_batch_create(all_items, cfg)
+
+
 def run_c3(args):
     """The 108 views (36 per operator) are one render list (an rc_batch built
     once, before timing: cameras, outputs and options are fixed; view i of
@@ -129,20 +157,14 @@ def run_c3(args):
     H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
     out = torch.empty((H, Wd, 4), dtype=torch.float32, device="cuda")
     opts = {op: c3_options(sc, op) for op in OPS}
-    outs = {op: [torch.empty((H, Wd, 4), dtype=torch.float32, device="cuda")
-                 for _ in sc.cameras] for op in OPS}
-    items = {op: [{"vol": vol, "camera": cam, "tf": tf, "shading": sc.shading,
-                   "options": opts[op], "out": o} for cam, o in zip(sc.cameras, outs[op])]
-             for op in OPS}
-    cache = os.path.join(ROOT, "_build", "batch_autotune.jsonl")
-    os.makedirs(os.path.dirname(cache), exist_ok=True)
-    all_items = [items[op][i] for i in range(len(sc.cameras)) for op in OPS]
-    cfg_all = rc.rc_batch_autotune(all_items, cache)
-    batch_all = rc.rc_batch_create(all_items, cfg_all)
+    items, all_items = c3_render_list(sc, vol, tf)
+    outs = {op: [it["out"] for it in items[op]] for op in OPS}
+    cache = AUTOTUNE_CACHE
+    cfg_all, batch_all = c3_batch(all_items)
 
     def step(events=None):
+        # re-ingest; the brick ranges exist, so rc_update_volume rebuilds them
         rc.rc_update_volume(vol, src)
-        rc.rc_build_bricks(vol, 8)
         if events is None:
             rc.rc_batch_render(batch_all)
         else:
@@ -292,6 +314,114 @@ def run_c5(args):
         "fwd_bwd_over_fwd_time": round(ms_fb / ms_f, 2),
         "bwd_kernels_ms": round(ms_b, 3),
     }
+
+
+def run_c3_grad(args, sc, vol, tf):
+    """Forward + backward at the metric's size: four views (every ninth of the
+    orbit) of the 512^3 u16 phantom at 1024^2, Sobel3D with Blinn-Phong,
+    step 0.5, ERT 0.99.  Loss: L2 against the same views rendered with a
+    second table; dL/dvolume (float32, 512^3) and dL/dtable through the
+    hand-written adjoint, which lights every sample (an opacity-0 sample
+    still has a gradient in the table's opacity entries) and scatters the
+    64-tap stencil adjoint.  All views in one launch each way."""
+    cams = sc.cameras[::9][:4]
+    opt = c3_options(sc, "sobel3d")
+    H, Wd = cams[0]["height"], cams[0]["width"]
+    tf2 = to_dev(W.tf_ramps(sc.tf.shape[0], seed=303, alpha_max=0.25, lo=0.1, hi=0.8))
+    targets = rc.rc_render_views(vol, cams, tf2, sc.shading, opt)
+    outs = [torch.empty((H, Wd, 4), dtype=torch.float32, device="cuda") for _ in cams]
+    auxes = [rc.new_aux(c) for c in cams]
+    grads = [torch.empty_like(o) for o in outs]
+    gv = torch.zeros((512, 512, 512), dtype=torch.float32, device="cuda")
+    gt = torch.zeros_like(tf)
+
+    def fwd():
+        rc.rc_render_views(vol, cams, tf, sc.shading, opt, outs=outs, auxes=auxes)
+
+    def fwd_bwd():
+        fwd()
+        for g, o, t in zip(grads, outs, targets):
+            torch.sub(o, t, out=g).mul_(2.0)
+        gv.zero_()
+        gt.zero_()
+        rc.rc_render_backward_views(vol, cams, tf, sc.shading, opt, auxes, grads, gv, gt)
+
+    def timeit(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    st = rc.new_stats()
+    for cam in cams:
+        rc.rc_render(vol, cam, tf, sc.shading, opt, stats=st)
+    lattice = int(st[0].item())
+    ms_f = timeit(fwd, 3)
+    ms_fb = timeit(fwd_bwd, 2)
+    nz = int((gv != 0).sum().item())
+    return {"workload": "512^3 u16 phantom -> 1024^2, 4 orbit views (0, 90, 180, 270 deg), "
+                        "Sobel3D Blinn-Phong, step 0.5, ERT 0.99; L2 loss vs a second table's "
+                        "images; dL/dvolume 512^3 f32 and dL/dtable 4096x4",
+            "views": len(cams), "lattice_samples": lattice,
+            "fwd_ms": round(ms_f, 3), "fwd_bwd_ms": round(ms_fb, 3),
+            "fwd_gsamples_s": round(lattice / ms_f / 1e6, 3),
+            "fwd_bwd_gsamples_s": round(lattice / ms_fb / 1e6, 3),
+            "fwd_bwd_over_fwd_time": round(ms_fb / ms_f, 2),
+            "grad_volume_nonzero": nz}
+
+
+def run_adaptive(args, sc, vol, tf):
+    """Adaptive sampling on the headline orbit: Sobel3D, samples in bricks
+    whose value range is at most 120 raw units (about six noise sigmas)
+    advance 4 steps, with opacity corrected to the distance; all 36 views
+    in one persistent launch, against the fixed-step orbit launch of the
+    same views.  Error = |adaptive - fixed step| per channel over all
+    pixels of all views."""
+    opt_f = c3_options(sc, "sobel3d")
+    opt_a = dict(opt_f, adapt_factor=4, adapt_range=120.0)
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    outs_f = [torch.empty((H, Wd, 4), dtype=torch.float32, device="cuda") for _ in sc.cameras]
+    outs_a = [torch.empty_like(o) for o in outs_f]
+
+    def timeit(fn, n=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    ms_f = timeit(lambda: rc.rc_render_views(vol, sc.cameras, tf, sc.shading, opt_f, outs=outs_f))
+    ms_a = timeit(lambda: rc.rc_render_views(vol, sc.cameras, tf, sc.shading, opt_a, outs=outs_a))
+    st_f, st_a = rc.new_stats(), rc.new_stats()
+    for cam in sc.cameras:
+        rc.rc_render(vol, cam, tf, sc.shading, opt_f, stats=st_f)
+        rc.rc_render(vol, cam, tf, sc.shading, opt_a, stats=st_a)
+    err_max, err_sum, n = 0.0, 0.0, 0
+    for a, f in zip(outs_a, outs_f):
+        d = (a - f).abs()
+        err_max = max(err_max, float(d.max().item()))
+        err_sum += float(d.sum().item())
+        n += d.numel()
+    lat_f, lat_a = int(st_f[0].item()), int(st_a[0].item())
+    return {"workload": "512^3 u16 phantom -> 1024^2, 36-view orbit, Sobel3D Blinn-Phong, step 0.5, "
+                        "ERT 0.99, skipping; adaptive factor 4 in bricks of range <= 120",
+            "adaptive_ms_per_view": round(ms_a / len(sc.cameras), 4),
+            "fixed_ms_per_view": round(ms_f / len(sc.cameras), 4),
+            "adaptive_samples": lat_a, "fixed_lattice_samples": lat_f,
+            "adaptive_gsamples_s": round(lat_a / ms_a / 1e6, 3),
+            "fixed_gsamples_s": round(lat_f / ms_f / 1e6, 3),
+            "speedup_vs_fixed": round(ms_f / ms_a, 3),
+            "max_abs_err_vs_fixed": round(err_max, 5),
+            "mean_abs_err_vs_fixed": round(err_sum / n, 7)}
 
 
 def run_c4(args):
@@ -504,9 +634,10 @@ def main():
     ap.add_argument("--no-per-op", action="store_true",
                     help="skip the per-operator orbit launches (profiling runs: every "
                          "raycast_batch dispatch is then the step's)")
-    ap.add_argument("--only", choices=["c4", "c5", "surface"], default=None,
-                    help="run only the batched (c4), differentiable (c5) or first-hit surface "
-                         "form and print it")
+    ap.add_argument("--only", choices=["c4", "c5", "surface", "adaptive", "c3grad"],
+                    default=None,
+                    help="run only the batched (c4), differentiable (c5 or c3grad), first-hit "
+                         "surface or adaptive form and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -519,6 +650,13 @@ def main():
     if args.calib_copy:
         calib_copy()
     if args.only:
+        if args.only in ("adaptive", "c3grad"):
+            sc = W.config_c3(n_views=args.views)
+            vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+            rc.rc_build_bricks(vol, 8)
+            fn = run_adaptive if args.only == "adaptive" else run_c3_grad
+            print(json.dumps(fn(args, sc, vol, to_dev(sc.tf))), flush=True)
+            return
         fn = {"c4": run_c4, "c5": run_c5, "surface": run_surface}[args.only]
         print(json.dumps(fn(args)), flush=True)
         return
@@ -574,6 +712,10 @@ def main():
         result["batched"] = run_c4(args)
         log("bench: first-hit surface form")
         result["surface"] = run_surface(args, sc, vol, tf)
+        log("bench: adaptive sampling")
+        result["adaptive"] = run_adaptive(args, sc, vol, tf)
+        log("bench: forward + backward at 512^3 -> 1024^2")
+        result["differentiable_c3"] = run_c3_grad(args, sc, vol, tf)
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
         result["cpu_baseline"] = cpu_baseline(sc, counts)

@@ -116,8 +116,8 @@ typedef struct {
                                  any other by one; each sample's opacity is corrected to the
                                  distance it stands for, relative to opacity_ref_step or, if
                                  that is 0, to `step`.  Samples are taken while t <= t_out.
-                                 Needs rc_build_bricks; rc_render only (batched, multi-view and
-                                 reverse calls return RC_E_UNSUPPORTED). */
+                                 Needs rc_build_bricks.  Forward calls only (single, multi-view,
+                                 batched); the reverse calls return RC_E_UNSUPPORTED. */
     float adapt_range;        /* raw-value range up to which a brick counts as detail-poor */
 } rc_options;
 
@@ -238,18 +238,33 @@ typedef struct {
     rc_aux* aux_dev;            /* NULL or device [height][width] */
 } rc_batch_item;
 
-/* Launch shape of the persistent kernel. */
+/* Launch shape of the persistent kernel and the shape of the voxel boxes
+ * its waves stage in LDS.  A wave marches its 64 rays in chunks of ray
+ * parameter; each chunk's voxel box (the chunk's cells plus the stencil
+ * apron) is staged in LDS.  The box budgets cap a chunk's box in bytes per
+ * wave (the chunk length halves until its box fits); every wave of the
+ * launch holds the largest budget its items use, so the budgets also set
+ * how many waves fit on a compute unit.  The images do not depend on any
+ * of these fields (bit-identical to rc_render). */
 typedef struct {
     int32_t tile_w;             /* tile width in pixels: 4, 8, 16 or 32 (tiles hold 64 pixels) */
     int32_t waves_per_wg;       /* waves per workgroup: 1, 2 or 4 */
     int32_t wg_per_cu;          /* resident workgroups per compute unit: 1 .. 32 */
     int32_t order;              /* 0: items in the given order; 1: largest images first */
+    int32_t box_bytes_grad;     /* LDS box budget per wave of Sobel3D / Zucker-Hummel items
+                                   (boxes of FP32 voxels): 0 = 12288, else a multiple of 1024
+                                   in 2048 .. 32768 */
+    int32_t box_bytes_cd;       /* the same for central-difference items (boxes in the volume's
+                                   own type): 0 = 8192, else as above */
+    int32_t chunk_len;          /* first chunk length in lattice samples (later chunks adapt):
+                                   0 = 16, else 4 .. 64; waves_per_wg times the largest budget
+                                   in use must not exceed 65536 */
 } rc_batch_config;
 
 typedef struct rc_batch rc_batch;   /* opaque: descriptors, queue, masks, captured graph */
 
 /* Validate every item as rc_render would, upload the descriptors and
- * allocate the queue and mask scratch.  cfg NULL = {8, 1, 8, 1}.  Items
+ * allocate the queue and mask scratch.  cfg NULL = {8, 1, 8, 1, 0, 0, 0}.  Items
  * that share a volume and a table (the views of an orbit) share one
  * empty-brick mask.  The images are bit-identical to rc_render's.  The
  * items' volumes, tables and outputs must outlive the batch.
@@ -272,11 +287,18 @@ void rc_batch_destroy(rc_batch* b);
 rc_status rc_render_batch(const rc_batch_item* items, int n, const rc_batch_config* cfg,
                           void* stream);
 
-/* Time candidate launch shapes (tile width, waves per workgroup, resident
- * workgroups, order) on these items and return the fastest in *out.  If
- * cache_path is not NULL, results are kept there as JSON lines keyed by a
- * hash of the items' shapes; a hit returns without timing.  Renders into
- * the items' outputs while timing.  Synchronises `stream`.
+/* Time candidate configurations on these items and return the fastest in
+ * *out.  The search runs in three stages, each keeping the best so far:
+ * launch shapes (tile width 8/16/4, 1 or 4 waves per workgroup, 4/8/16
+ * resident waves per compute unit, both orders) with the default boxes;
+ * then the LDS box budgets of the operator kinds present (8, 12, 16 or 20
+ * KiB for Sobel3D / Zucker-Hummel, 4, 8 or 12 KiB for central differences);
+ * then the first chunk length (8, 16 or 32).  If cache_path is not NULL,
+ * results are kept there as JSON lines keyed by a hash of the items' shapes
+ * (volume sizes and types, image sizes, operator, shading, options); a hit
+ * returns without timing.  Renders into the items' outputs while timing.
+ * Synchronises `stream`.  (This is the autotuner of the batched form; it
+ * takes the batch's own items, so it carries the rc_batch_ prefix.)
  * Errors: as rc_batch_create, plus RC_E_INVALID for an unwritable cache. */
 rc_status rc_batch_autotune(const rc_batch_item* items, int n, const char* cache_path,
                             void* stream, rc_batch_config* out);
@@ -287,8 +309,7 @@ rc_status rc_batch_autotune(const rc_batch_item* items, int n, const char* cache
  * images share the GPU.  Equivalent to n_views rc_render /
  * rc_render_backward calls (Section 3.10: rays are independent).  The
  * forward goes through the persistent kernel of the batch API: its images
- * are bit-identical to rc_render's.  Adaptive sampling is rc_render only
- * (RC_E_UNSUPPORTED).
+ * are bit-identical to rc_render's, adaptive sampling included.
  * ---------------------------------------------------------------------- */
 /*   cams      host array [n_views]
  *   out_rgba  host array [n_views] of device pointers, [H_v][W_v][4] each

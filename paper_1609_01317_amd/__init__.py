@@ -94,7 +94,11 @@ class rc_batch_item(C.Structure):
 
 class rc_batch_config(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("waves_per_wg", C.c_int32), ("wg_per_cu", C.c_int32),
-                ("order", C.c_int32)]
+                ("order", C.c_int32), ("box_bytes_grad", C.c_int32), ("box_bytes_cd", C.c_int32),
+                ("chunk_len", C.c_int32)]
+
+
+BATCH_CONFIG_FIELDS = [f for f, _ in rc_batch_config._fields_]
 
 
 _lib = None
@@ -400,10 +404,11 @@ def _batch_items(items):
 
 
 def _config(cfg):
+    """dict -> rc_batch_config; the box budgets and chunk length default to 0
+    (the library's defaults)."""
     if cfg is None:
         return None
-    return C.byref(rc_batch_config(int(cfg["tile_w"]), int(cfg["waves_per_wg"]),
-                                   int(cfg["wg_per_cu"]), int(cfg["order"])))
+    return C.byref(rc_batch_config(*[int(cfg.get(f, 0)) for f in BATCH_CONFIG_FIELDS]))
 
 
 class Batch:
@@ -447,8 +452,7 @@ def rc_batch_autotune(items, cache_path=None, stream=None) -> dict:
     out = rc_batch_config()
     path = cache_path.encode() if cache_path else None
     _check(_L().rc_batch_autotune(arr, len(items), path, _stream(stream), C.byref(out)))
-    return {"tile_w": out.tile_w, "waves_per_wg": out.waves_per_wg, "wg_per_cu": out.wg_per_cu,
-            "order": out.order}
+    return {f: int(getattr(out, f)) for f in BATCH_CONFIG_FIELDS}
 
 
 # ---------------------------------------------------------------- several views of one volume
@@ -460,6 +464,11 @@ def rc_render_views(vol: Volume, cameras, tf: torch.Tensor, shading: dict, optio
                     outs=None, auxes=None, stream=None):
     """Render len(cameras) views in as few launches as possible; returns the
     list of [H,W,4] outputs."""
+    return _render_views("rc_render_views", vol, cameras, tf, shading, options, outs, auxes,
+                         stream)
+
+
+def _render_views(fn, vol, cameras, tf, shading, options, outs, auxes, stream):
     _check_tf(tf)
     n = len(cameras)
     if outs is None:
@@ -472,8 +481,8 @@ def rc_render_views(vol: Volume, cameras, tf: torch.Tensor, shading: dict, optio
     cams = (rc_camera * n)(*[camera_struct(c) for c in cameras])
     sh, opt = shading_struct(shading), options_struct(options)
     aux_arr = _ptr_array(auxes) if auxes is not None else None
-    _check(_L().rc_render_views(vol.handle, cams, n, _ptr(tf), tf.shape[0], C.byref(sh),
-                                C.byref(opt), _ptr_array(outs), aux_arr, _stream(stream)))
+    _check(getattr(_L(), fn)(vol.handle, cams, n, _ptr(tf), tf.shape[0], C.byref(sh),
+                             C.byref(opt), _ptr_array(outs), aux_arr, _stream(stream)))
     return outs
 
 

@@ -15,7 +15,7 @@
 #include <string>
 #include <vector>
 
-#include "march.h"
+#include "persist.h"
 
 namespace rc {
 
@@ -116,49 +116,6 @@ __global__ __launch_bounds__(256) void batch_super(const MaskJob* __restrict__ j
     super_all[g] = all;
 }
 
-// The persistent kernel.  `kind` selects the instantiation per work unit
-// (uniform across the wave): dtype * 3 + gradient operator for shaded items,
-// 9 + dtype for unshaded ones.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void raycast_batch(const RenderParams* __restrict__ items,
-                                                     const int* __restrict__ kinds,
-                                                     const int* __restrict__ tile_off,
-                                                     const int* __restrict__ order, int n,
-                                                     int total, int* __restrict__ counter,
-                                                     int lds_bytes) {
-    extern __shared__ __align__(16) unsigned char lds_all[];
-    const int lane = threadIdx.x & 63;
-    unsigned char* lds = lds_all + (threadIdx.x >> 6) * lds_bytes;
-    for (;;) {
-        int w = 0;
-        if (lane == 0) w = atomicAdd(counter, 1);
-        w = __builtin_amdgcn_readfirstlane(__shfl(w, 0));
-        if (w >= total) break;
-        int lo = 0, hi = n;
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (tile_off[mid] <= w) lo = mid; else hi = mid;
-        }
-        int item = __builtin_amdgcn_readfirstlane(order[lo]);
-        int tile = w - tile_off[lo];
-        const RenderParams& P = items[item];
-        switch (kinds[item]) {
-            case 0: render_tile<uint8_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 1: render_tile<uint8_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 2: render_tile<uint8_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 3: render_tile<uint16_t, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 4: render_tile<uint16_t, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 5: render_tile<uint16_t, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 6: render_tile<float, RC_GRAD_CENTRAL, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 7: render_tile<float, RC_GRAD_SOBEL3D, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 8: render_tile<float, RC_GRAD_ZUCKER_HUMMEL, true>(P, P.view, tile, lane, lds, lds_bytes); break;
-            // unshaded items: no gradient, one instantiation per voxel type
-            case 9: render_tile<uint8_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, lds, lds_bytes); break;
-            case 10: render_tile<uint16_t, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, lds, lds_bytes); break;
-            default: render_tile<float, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane, lds, lds_bytes); break;
-        }
-    }
-}
-
 }  // namespace rc
 
 using namespace rc;
@@ -173,6 +130,7 @@ struct rc_batch {
     long long total_super;
     int grid;
     int lds_bytes;              // LDS box budget per wave
+    const PersistKernel* kernel;    // the instantiation for the items' kinds
     void* dmem;                 // one allocation holding everything below
     RenderParams* d_items;
     int* d_kinds;
@@ -188,6 +146,8 @@ struct rc_batch {
     bool captured;
 };
 
+static bool box_ok(int b) { return b == 0 || (b >= 2048 && b <= 32768 && b % 1024 == 0); }
+
 static rc_status check_config(const rc_batch_config& c) {
     if (c.tile_w != 4 && c.tile_w != 8 && c.tile_w != 16 && c.tile_w != 32)
         return fail(RC_E_INVALID, "batch config: tile_w must be 4, 8, 16 or 32");
@@ -196,10 +156,25 @@ static rc_status check_config(const rc_batch_config& c) {
     if (c.wg_per_cu < 1 || c.wg_per_cu > 32)
         return fail(RC_E_INVALID, "batch config: wg_per_cu must be 1..32");
     if (c.order != 0 && c.order != 1) return fail(RC_E_INVALID, "batch config: order must be 0/1");
+    if (!box_ok(c.box_bytes_grad) || !box_ok(c.box_bytes_cd))
+        return fail(RC_E_INVALID,
+                    "batch config: box budgets must be 0 or a multiple of 1024 in 2048..32768");
+    if (c.chunk_len != 0 && (c.chunk_len < 4 || c.chunk_len > 64))
+        return fail(RC_E_INVALID, "batch config: chunk_len must be 0 or 4..64");
     return RC_OK;
 }
 
-static rc_batch_config default_config() { return rc_batch_config{8, 1, 8, 1}; }
+static rc_batch_config default_config() { return rc_batch_config{8, 1, 8, 1, 0, 0, 0}; }
+
+// The box budget of an item: FP32 boxes for the 64-voxel stencils, boxes of
+// the volume's type for central differences, nothing for unshaded items
+// (they read the bricked volume directly).
+static int item_box_bytes(const rc_batch_item& it, const rc_batch_config& c) {
+    if (it.sh.model == RC_SHADE_NONE || it.opt.adapt_factor > 1) return 16;
+    if (it.opt.gradient_op == RC_GRAD_CENTRAL)
+        return c.box_bytes_cd ? c.box_bytes_cd : kBatchWaveLdsBytes;
+    return c.box_bytes_grad ? c.box_bytes_grad : kWaveLdsBytes;
+}
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -223,14 +198,13 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
         if (st != RC_OK) return fail(st, "item %d: %s", i, rc_last_error());
         if (!it.out_rgba_dev) return fail(RC_E_INVALID, "item %d: out_rgba_dev is NULL", i);
         if (it.reserved != 0) return fail(RC_E_INVALID, "item %d: reserved field must be 0", i);
-        if (it.opt.adapt_factor > 1)
-            return fail(RC_E_UNSUPPORTED, "item %d: adaptive sampling is rc_render only", i);
         fill_render_params(P[i], it.vol, &it.cam, it.tf_rgba_dev, it.tf_len, &it.sh, &it.opt);
         set_tiling(P[i].view, c.tile_w);
+        P[i].box_bytes = item_box_bytes(it, c);
+        P[i].chunk_init = c.chunk_len ? c.chunk_len : kChunkInit;
         P[i].view.out = (float4*)it.out_rgba_dev;
         P[i].view.aux = it.aux_dev;
-        kinds[i] = it.sh.model == RC_SHADE_NONE ? 9 + (int)it.vol->dtype
-                                                : (int)it.vol->dtype * 3 + it.opt.gradient_op;
+        kinds[i] = item_kind(it.vol, &it.sh, &it.opt);
         tiles[i] = P[i].view.n_tiles;
         if (it.opt.skip_empty) {
             const auto key = std::make_tuple((const void*)it.vol, (const void*)it.tf_rgba_dev,
@@ -265,6 +239,12 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
             jobs.push_back(J);
         }
     }
+    // every wave holds the largest box budget its items use
+    int lds_bytes = 16;
+    for (int i = 0; i < n; ++i) lds_bytes = std::max(lds_bytes, P[i].box_bytes);
+    if ((long long)lds_bytes * c.waves_per_wg > 65536)
+        return fail(RC_E_INVALID, "rc_batch_create: %d waves x %d LDS bytes exceed 64 KiB",
+                    c.waves_per_wg, lds_bytes);
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     if (c.order == 1)
@@ -340,13 +320,10 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     if (e != hipSuccess || cus < 1) cus = 256;
     b->grid = cus * c.wg_per_cu;
-    // Sobel3D / Zucker-Hummel items stage FP32 boxes: the single-image budget
-    // (measured +9 % on a 512^3 orbit); batches of central-difference or
-    // unshaded items keep the smaller one (measured better on small volumes)
-    b->lds_bytes = kBatchWaveLdsBytes;
-    for (int i = 0; i < n; ++i)
-        if (items[i].sh.model != RC_SHADE_NONE && items[i].opt.gradient_op != RC_GRAD_CENTRAL)
-            b->lds_bytes = kWaveLdsBytes;
+    b->lds_bytes = lds_bytes;
+    unsigned mask = 0;
+    for (int i = 0; i < n; ++i) mask |= 1u << kinds[i];
+    b->kernel = &persist_kernel(mask);
     *out = b;
     return RC_OK;
 }
@@ -362,7 +339,7 @@ static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
         hipLaunchKernelGGL(batch_super, dim3(g), dim3(256), 0, s, b->d_jobs, b->n_jobs,
                            b->total_super, b->d_mask, b->d_super);
     }
-    hipLaunchKernelGGL(raycast_batch, dim3(b->grid), dim3(64 * b->cfg.waves_per_wg),
+    hipLaunchKernelGGL(b->kernel->fn, dim3(b->grid), dim3(64 * b->cfg.waves_per_wg),
                        (size_t)b->lds_bytes * b->cfg.waves_per_wg, s,
                        b->d_items, b->d_kinds, b->d_tile_off, b->d_order, b->n, b->total_tiles,
                        b->d_counter, b->lds_bytes);
@@ -371,11 +348,11 @@ static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
 }
 
 // Items already in device memory (built there by the caller's own kernel):
-// the queue reset and the persistent launch, one wave per workgroup and
-// three resident per SIMD.
+// the queue reset and the persistent launch, one wave per workgroup and as
+// many resident per SIMD as the chosen instantiation targets.
 rc_status rc::launch_batch_items(const RenderParams* items, const int* kinds, const int* tile_off,
                              const int* order, int n, int total, int* counter, int lds_bytes,
-                             hipStream_t s) {
+                             unsigned kind_mask, hipStream_t s) {
     // compute units per device, looked up once (threads may race to store
     // the same value)
     static std::atomic<int> cus[64];
@@ -388,8 +365,9 @@ rc_status rc::launch_batch_items(const RenderParams* items, const int* kinds, co
             n_cu = 256;
         cus[dev].store(n_cu, std::memory_order_relaxed);
     }
+    const PersistKernel& k = persist_kernel(kind_mask);
     hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL(raycast_batch, dim3((unsigned)(n_cu * 12)), dim3(64), (size_t)lds_bytes,
+    hipLaunchKernelGGL(k.fn, dim3((unsigned)(n_cu * 4 * k.waves)), dim3(64), (size_t)lds_bytes,
                        s, items, kinds, tile_off, order, n, total, counter, lds_bytes);
     RC_HIP(hipGetLastError());
     return RC_OK;
@@ -448,7 +426,7 @@ static unsigned long long fnv1a(const std::string& s) {
 }
 
 static std::string batch_key(const rc_batch_item* items, int n) {
-    std::string k = "v1;n=" + std::to_string(n) + ";";
+    std::string k = "v2;n=" + std::to_string(n) + ";";
     for (int i = 0; i < n; ++i) {
         const rc_batch_item& it = items[i];
         k += std::to_string(it.vol->nx) + "x" + std::to_string(it.vol->ny) + "x" +
@@ -463,29 +441,49 @@ static std::string batch_key(const rc_batch_item* items, int n) {
     return buf;
 }
 
+static bool read_int(const char* line, const char* name, int* v) {
+    std::string pat = std::string("\"") + name + "\":";
+    const char* p = strstr(line, pat.c_str());
+    return p && sscanf(p + pat.size(), " %d", v) == 1;
+}
+
 static bool cache_lookup(const char* path, const std::string& key, rc_batch_config* out) {
     FILE* f = fopen(path, "r");
     if (!f) return false;
-    char line[512];
+    char line[768];
     bool found = false;
     std::string needle = "\"key\": \"" + key + "\"";
     while (fgets(line, sizeof line, f)) {
         if (!strstr(line, needle.c_str())) continue;
         rc_batch_config c;
-        const char* p = strstr(line, "\"tile_w\":");
-        const char* q = strstr(line, "\"waves_per_wg\":");
-        const char* r = strstr(line, "\"wg_per_cu\":");
-        const char* o = strstr(line, "\"order\":");
-        if (p && q && r && o && sscanf(p, "\"tile_w\": %d", &c.tile_w) == 1 &&
-            sscanf(q, "\"waves_per_wg\": %d", &c.waves_per_wg) == 1 &&
-            sscanf(r, "\"wg_per_cu\": %d", &c.wg_per_cu) == 1 &&
-            sscanf(o, "\"order\": %d", &c.order) == 1 && check_config(c) == RC_OK) {
+        if (read_int(line, "tile_w", &c.tile_w) && read_int(line, "waves_per_wg", &c.waves_per_wg) &&
+            read_int(line, "wg_per_cu", &c.wg_per_cu) && read_int(line, "order", &c.order) &&
+            read_int(line, "box_bytes_grad", &c.box_bytes_grad) &&
+            read_int(line, "box_bytes_cd", &c.box_bytes_cd) &&
+            read_int(line, "chunk_len", &c.chunk_len) && check_config(c) == RC_OK) {
             *out = c;
             found = true;
         }
     }
     fclose(f);
     return found;
+}
+
+// Time one configuration: a warm-up render, then three timed renders.
+static rc_status time_config(const rc_batch_item* items, int n, const rc_batch_config& c,
+                             hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* ms) {
+    rc_batch* b = nullptr;
+    rc_status st = rc_batch_create(items, n, &c, s, &b);
+    if (st != RC_OK) return st;
+    st = enqueue_batch(b, s);
+    if (st == RC_OK && hipEventRecord(e0, s) != hipSuccess) st = RC_E_DEVICE;
+    for (int r = 0; r < 3 && st == RC_OK; ++r) st = enqueue_batch(b, s);
+    if (st == RC_OK && hipEventRecord(e1, s) != hipSuccess) st = RC_E_DEVICE;
+    if (st == RC_OK && hipEventSynchronize(e1) != hipSuccess) st = RC_E_DEVICE;
+    if (st == RC_OK && hipEventElapsedTime(ms, e0, e1) != hipSuccess) st = RC_E_DEVICE;
+    rc_batch_destroy(b);
+    if (st != RC_OK) return fail(st, "rc_batch_autotune: timing failed");
+    return RC_OK;
 }
 
 extern "C" rc_status rc_batch_autotune(const rc_batch_item* items, int n, const char* cache_path,
@@ -497,47 +495,75 @@ extern "C" rc_status rc_batch_autotune(const rc_batch_item* items, int n, const 
     std::string key = batch_key(items, n);
     if (cache_path && cache_lookup(cache_path, key, out)) return RC_OK;
     hipStream_t s = (hipStream_t)stream;
-    const int tws[] = {8, 16, 4};
-    const int wpw[] = {1, 4};
-    const int wpc[] = {4, 8, 16};
-    const int ords[] = {1, 0};
+    bool has_grad = false, has_cd = false;
+    for (int i = 0; i < n; ++i) {
+        if (items[i].sh.model == RC_SHADE_NONE) continue;
+        if (items[i].opt.gradient_op == RC_GRAD_CENTRAL) has_cd = true;
+        else has_grad = true;
+    }
     rc_batch_config best = default_config();
     float best_ms = INFINITY;
     hipEvent_t e0, e1;
     RC_HIP(hipEventCreate(&e0));
     RC_HIP(hipEventCreate(&e1));
     rc_status st = RC_OK;
+    auto trial = [&](const rc_batch_config& c) -> rc_status {
+        float ms = 0.0f;
+        rc_status r = time_config(items, n, c, s, e0, e1, &ms);
+        if (r == RC_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        return r;
+    };
+    // stage 1: launch shape, default boxes
+    const int tws[] = {8, 16, 4};
+    const int wpw[] = {1, 4};
+    const int wpc[] = {4, 8, 16};
+    const int ords[] = {1, 0};
     for (int tw : tws)
         for (int w : wpw)
             for (int pc : wpc)
-                for (int od : ords) {
-                    rc_batch_config c{tw, w, std::max(1, pc / w), od};
-                    rc_batch* b = nullptr;
-                    st = rc_batch_create(items, n, &c, stream, &b);
-                    if (st != RC_OK) goto done;
-                    float ms = 0.0f;
-                    st = enqueue_batch(b, s);                       // warm-up
-                    if (st == RC_OK && hipEventRecord(e0, s) != hipSuccess) st = RC_E_DEVICE;
-                    for (int r = 0; r < 3 && st == RC_OK; ++r) st = enqueue_batch(b, s);
-                    if (st == RC_OK && hipEventRecord(e1, s) != hipSuccess) st = RC_E_DEVICE;
-                    if (st == RC_OK && hipEventSynchronize(e1) != hipSuccess) st = RC_E_DEVICE;
-                    if (st == RC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = RC_E_DEVICE;
-                    rc_batch_destroy(b);
-                    if (st != RC_OK) { fail(st, "rc_batch_autotune: timing failed"); goto done; }
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = c;
-                    }
-                }
+                for (int od : ords)
+                    if (st == RC_OK) st = trial(rc_batch_config{tw, w, std::max(1, pc / w), od, 0, 0, 0});
+    // stage 2: box budgets of the kinds present (a budget too large for the
+    // shape's waves per workgroup is skipped)
+    if (st == RC_OK) {
+        const rc_batch_config shape = best;
+        const int grads[] = {8192, 12288, 16384, 20480};
+        const int cds[] = {4096, 8192, 12288};
+        for (int g : grads) {
+            if (!has_grad && g != grads[0]) break;
+            for (int d : cds) {
+                if (!has_cd && d != cds[0]) break;
+                rc_batch_config c = shape;
+                c.box_bytes_grad = has_grad ? g : 0;
+                c.box_bytes_cd = has_cd ? d : 0;
+                if ((long long)std::max(g, d) * c.waves_per_wg > 65536) continue;
+                if (st == RC_OK) st = trial(c);
+            }
+        }
+    }
+    // stage 3: first chunk length
+    if (st == RC_OK && (has_grad || has_cd)) {
+        const rc_batch_config boxes = best;
+        for (int len : {8, 32}) {
+            rc_batch_config c = boxes;
+            c.chunk_len = len;
+            if (st == RC_OK) st = trial(c);
+        }
+    }
+    if (st != RC_OK) goto done;
     *out = best;
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (!f) { st = fail(RC_E_INVALID, "rc_batch_autotune: cannot write %s", cache_path); goto done; }
         fprintf(f,
                 "{\"key\": \"%s\", \"tile_w\": %d, \"waves_per_wg\": %d, \"wg_per_cu\": %d, "
-                "\"order\": %d, \"ms_per_batch\": %.4f, \"items\": %d}\n",
+                "\"order\": %d, \"box_bytes_grad\": %d, \"box_bytes_cd\": %d, "
+                "\"chunk_len\": %d, \"ms_per_batch\": %.4f, \"items\": %d}\n",
                 key.c_str(), best.tile_w, best.waves_per_wg, best.wg_per_cu, best.order,
-                best_ms / 3.0f, n);
+                best.box_bytes_grad, best.box_bytes_cd, best.chunk_len, best_ms / 3.0f, n);
         fclose(f);
     }
 done:

@@ -929,8 +929,8 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
                              (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
     using LT = typename LdsT<VT, OP>::type;
     LT* lds = (LT*)lds_raw;
-    const int cap = lds_bytes / (int)sizeof(LT);
-    int len = kChunkInit;
+    const int cap = min(lds_bytes, P.box_bytes) / (int)sizeof(LT);
+    int len = P.chunk_init;
     // a super-chunk is tried at the start and after every empty chunk
     bool try_super = P.skip && P.super_empty != nullptr;
     // Every chunk advances at least the lane that owns the earliest pending
@@ -1040,7 +1040,7 @@ __device__ inline void render_tile(const RenderParams& P, const ViewParams& V, i
     const int tw = V.tile_w, th = 64 / V.tile_w;
     int tx = tile % V.tiles_x, ty = tile / V.tiles_x;
     int px = tx * tw + (lane % tw), py = ty * th + (lane / tw);
-    bool valid = px < V.W && py < V.H;
+    bool valid = px >= 0 && py >= 0 && px < V.W && py < V.H;
     Ray R;
     R.K = -1;
     R.t_in = R.t_out = 0.0;

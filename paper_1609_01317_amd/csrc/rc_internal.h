@@ -114,6 +114,10 @@ struct RenderParams {
     int nsx, nsy, nsz;          // super-bricks per axis
     rc_stats* stats;            // kStatSlots consecutive copies, or null
     unsigned int* dbg;          // bounds-checked build: violation counter; else null
+    // chunk shape: LDS bytes a chunk's box may take (capped by the wave's
+    // allocation) and the first chunk length in lattice samples
+    int box_bytes;
+    int chunk_init;
 };
 
 // Several images of one volume in one launch (kernel-argument block).
@@ -149,10 +153,24 @@ unsigned int* debug_counter();
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
 // The persistent batched kernel over n items already in device memory
 // (queue reset included); total = the items' tiles, kinds/order as in
-// rc_batch_create.
+// rc_batch_create, kind_mask = the set of the items' kinds (bit per kind).
 rc_status launch_batch_items(const RenderParams* items, const int* kinds, const int* tile_off,
                              const int* order, int n, int total, int* counter, int lds_bytes,
-                             hipStream_t s);
+                             unsigned kind_mask, hipStream_t s);
+// Several views of one volume (rc_render_views and its allocation-free
+// variant): argument checks, the scratch the call needs, and the enqueue
+// with that scratch supplied by the caller.
+size_t views_scratch_bytes(const rc_volume* v, int tf_len, const rc_options* opt);
+rc_status check_views_args(const rc_volume* v, const rc_camera* cams, int n_views,
+                           const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                           const rc_options* opt, float* const* out_rgba, const char* who);
+rc_status render_views_into(const rc_volume* v, const rc_camera* cams, int n_views,
+                            const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                            const rc_options* opt, float* const* out_rgba, rc_aux* const* aux,
+                            char* scratch, hipStream_t s);
+// The batched kernel's instantiation of an item: dtype * 3 + operator
+// (shaded), 9 + dtype (unshaded), 12 + dtype * 3 + operator (adaptive).
+int item_kind(const rc_volume* v, const rc_shading* sh, const rc_options* opt);
 // per-lane adaptive-step march (P.adapt > 1)
 rc_status launch_adaptive(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
 

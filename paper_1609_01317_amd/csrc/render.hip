@@ -1,7 +1,7 @@
 // Forward render: argument checks, the per-render empty-brick mask and the
 // raycast kernel (one ray per pixel, Section 3.10).
+#include <atomic>
 #include <cmath>
-#include <mutex>
 
 #include "march.h"
 
@@ -331,24 +331,25 @@ static double op_gain(int op) {
 }
 
 // ---------------------------------------------------------------- bounds-checked build
-// One violation counter per device, allocated on first use; null in the
+// One violation counter per device: a file-scope device variable (zero at
+// load), whose address on each device is looked up once; null in the
 // product build.
 #ifdef RC_DEBUG_BOUNDS
-static unsigned int* g_dbg[64] = {nullptr};
-static std::mutex g_dbg_lock;
+static __device__ unsigned int g_dbg_count;
+static std::atomic<unsigned int*> g_dbg[64];
 #endif
 unsigned int* debug_counter() {
 #ifdef RC_DEBUG_BOUNDS
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> guard(g_dbg_lock);
-    if (!g_dbg[dev]) {
-        unsigned int* p = nullptr;
-        if (hipMalloc(&p, sizeof(unsigned int)) != hipSuccess) return nullptr;
-        if (hipMemset(p, 0, sizeof(unsigned int)) != hipSuccess) return nullptr;
-        g_dbg[dev] = p;
+    unsigned int* p = g_dbg[dev].load(std::memory_order_acquire);
+    if (!p) {
+        void* q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(g_dbg_count)) != hipSuccess) return nullptr;
+        p = (unsigned int*)q;
+        g_dbg[dev].store(p, std::memory_order_release);
     }
-    return g_dbg[dev];
+    return p;
 #else
     return nullptr;
 #endif
@@ -438,6 +439,8 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     P.nsz = v->nsz;
     P.stats = nullptr;
     P.dbg = debug_counter();
+    P.box_bytes = kWaveLdsBytes;
+    P.chunk_init = kChunkInit;
 }
 
 }  // namespace rc
@@ -494,37 +497,63 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
     return st;
 }
 
+namespace rc {
+
+// ---------------------------------------------------------------- several views
 // Several views of one volume, table, shading and options in as few launches
-// as possible (up to kMaxViews views per launch).
-extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, int n_views,
-                                     const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
-                                     const rc_options* opt, float* const* out_rgba,
-                                     rc_aux* const* aux, void* stream) {
-    if (!cams || !out_rgba) return fail(RC_E_INVALID, "rc_render_views: cams/out_rgba is NULL");
-    if (n_views < 1) return fail(RC_E_INVALID, "rc_render_views: n_views must be >= 1");
+// as possible (up to kMaxViews views per launch).  The per-call scratch
+// holds the items of one launch, their kinds, tile offsets, order and the
+// work counter, then the skip masks.
+size_t views_scratch_bytes(const rc_volume* v, int tf_len, const rc_options* opt) {
+    const size_t items_bytes = ((sizeof(RenderParams) * kMaxViews + 255) / 256) * 256;
+    const size_t queue_bytes = 256 * 4;
+    size_t mask_bytes = 0, super_bytes = 0, skip_bytes = 0;
+    if (opt->skip_empty) skip_bytes = skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes);
+    return items_bytes + queue_bytes + skip_bytes;
+}
+
+rc_status check_views_args(const rc_volume* v, const rc_camera* cams, int n_views,
+                           const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                           const rc_options* opt, float* const* out_rgba, const char* who) {
+    if (!cams || !out_rgba) return fail(RC_E_INVALID, "%s: cams/out_rgba is NULL", who);
+    if (n_views < 1) return fail(RC_E_INVALID, "%s: n_views must be >= 1", who);
     for (int i = 0; i < n_views; ++i) {
         rc_status st = check_render_args(v, &cams[i], tf_rgba_dev, tf_len, sh, opt);
         if (st != RC_OK) return fail(st, "view %d: %s", i, rc_last_error());
         if (!out_rgba[i]) return fail(RC_E_INVALID, "view %d: out_rgba is NULL", i);
     }
-    if (opt->adapt_factor > 1)
-        return fail(RC_E_UNSUPPORTED, "rc_render_views: adaptive sampling is rc_render only");
-    hipStream_t s = (hipStream_t)stream;
+    return RC_OK;
+}
+
+int item_kind(const rc_volume* v, const rc_shading* sh, const rc_options* opt) {
+    if (opt->adapt_factor > 1) return 12 + (int)v->dtype * 3 + opt->gradient_op;
+    if (sh->model == RC_SHADE_NONE) return 9 + (int)v->dtype;
+    return (int)v->dtype * 3 + opt->gradient_op;
+}
+
+// The enqueue part of rc_render_views, with `scratch` (device memory of at
+// least views_scratch_bytes, 256-byte aligned) supplied by the caller.
+// Everything in it is written by this call's kernels before it is read: the
+// skip masks by the mask kernels, the items by pack_views, the counter by
+// the batch kernel's reset.
+rc_status render_views_into(const rc_volume* v, const rc_camera* cams, int n_views,
+                            const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                            const rc_options* opt, float* const* out_rgba, rc_aux* const* aux,
+                            char* scratch, hipStream_t s) {
     RenderParams P;
     fill_render_params(P, v, &cams[0], tf_rgba_dev, tf_len, sh, opt);
     const bool lit = sh->model != RC_SHADE_NONE;
-    const int kind = lit ? (int)v->dtype * 3 + opt->gradient_op : 9 + (int)v->dtype;
-    const int lds_bytes =
-        lit && opt->gradient_op != RC_GRAD_CENTRAL ? kWaveLdsBytes : kBatchWaveLdsBytes;
-    // scratch: the items of one launch, then their kinds, tile offsets,
-    // order and the work counter, then the skip masks
+    const int kind = item_kind(v, sh, opt);
+    // unshaded and adaptive marches stage nothing
+    const int lds_bytes = opt->adapt_factor > 1 || !lit ? 16
+                          : opt->gradient_op != RC_GRAD_CENTRAL ? kWaveLdsBytes
+                                                                : kBatchWaveLdsBytes;
+    P.box_bytes = lds_bytes;
     const size_t items_bytes = ((sizeof(RenderParams) * kMaxViews + 255) / 256) * 256;
     const size_t queue_bytes = 256 * 4;
-    size_t mask_bytes = 0, super_bytes = 0, skip_bytes = 0;
-    if (opt->skip_empty) skip_bytes = skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes);
-    void* scratch = nullptr;
-    RC_HIP(hipMallocAsync(&scratch, items_bytes + queue_bytes + skip_bytes, s));
-    char* base = (char*)scratch;
+    size_t mask_bytes = 0, super_bytes = 0;
+    if (opt->skip_empty) (void)skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes);
+    char* base = scratch;
     RenderParams* items = (RenderParams*)base;
     int* kinds = (int*)(base + items_bytes);
     int* tile_off = (int*)(base + items_bytes + 256);
@@ -558,8 +587,26 @@ extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, 
             st = hip_fail(e, "pack_views");
             break;
         }
-        st = launch_batch_items(items, kinds, tile_off, order, S.n, total, counter, lds_bytes, s);
+        st = launch_batch_items(items, kinds, tile_off, order, S.n, total, counter, lds_bytes,
+                                1u << kind, s);
     }
+    return st;
+}
+
+}  // namespace rc
+
+extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, int n_views,
+                                     const float* tf_rgba_dev, int tf_len, const rc_shading* sh,
+                                     const rc_options* opt, float* const* out_rgba,
+                                     rc_aux* const* aux, void* stream) {
+    rc_status st = check_views_args(v, cams, n_views, tf_rgba_dev, tf_len, sh, opt, out_rgba,
+                                    "rc_render_views");
+    if (st != RC_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    void* scratch = nullptr;
+    RC_HIP(hipMallocAsync(&scratch, views_scratch_bytes(v, tf_len, opt), s));
+    st = render_views_into(v, cams, n_views, tf_rgba_dev, tf_len, sh, opt, out_rgba, aux,
+                           (char*)scratch, s);
     hipError_t e = hipFreeAsync(scratch, s);
     if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return st;

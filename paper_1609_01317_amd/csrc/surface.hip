@@ -57,7 +57,8 @@ __global__ __launch_bounds__(64) void raycast_surface(RenderParams P, SurfacePar
         if (S.range) {
             int b0 = clampi(C.c[0], 0, P.nx - 1) >> 3, b1 = clampi(C.c[1], 0, P.ny - 1) >> 3,
                 b2 = clampi(C.c[2], 0, P.nz - 1) >> 3;
-            float2 r = S.range[(b2 * P.nby + b1) * P.nbx + b0];
+            float2 r = S.range[RC_IDX(P.dbg, (b2 * P.nby + b1) * P.nbx + b0,
+                                      (long long)P.nbx * P.nby * P.nbz)];
             if (r.y < S.skip_lo || r.x > S.skip_hi) continue;
         }
         if (in_window(S, value_of<VT>(src, C))) {
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(64) void raycast_surface(RenderParams P, SurfacePar
     }
     long long pix = (long long)py * V.W + px;
     V.out[RC_IDX(P.dbg, pix, (long long)V.W * V.H)] = out;
-    if (S.t_hit) S.t_hit[pix] = t_hit;
+    if (S.t_hit) S.t_hit[RC_IDX(P.dbg, pix, (long long)V.W * V.H)] = t_hit;
 }
 
 template <typename VT>

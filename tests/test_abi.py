@@ -42,7 +42,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(rc.rc_options) == 8 + 6 * 8 + 8 * 4
     assert C.sizeof(rc.rc_stats) == 64
     assert C.sizeof(rc.rc_batch_item) == 272
-    assert C.sizeof(rc.rc_batch_config) == 16
+    assert C.sizeof(rc.rc_batch_config) == 28
     assert C.sizeof(rc.rc_surface_options) == 8 + 6 * 8 + 2 * 4 + 4 * 4
 
 
@@ -122,3 +122,17 @@ def test_surface_rejects_bad_arguments_on_host():
     st, msg = _status("rc_render_surface", None, C.byref(cam), tf, 256, C.byref(sh), C.byref(opt),
                       out, None, None)
     assert st == rc.RC_E_INVALID and "volume" in msg
+
+
+def test_batch_config_rejected_on_host():
+    """Box budgets and chunk lengths outside their ranges are refused before
+    any item is looked at (no device work)."""
+    items = (rc.rc_batch_item * 1)()
+    out = C.c_void_p()
+    base = dict(tile_w=8, waves_per_wg=1, wg_per_cu=8, order=1)
+    for bad in (dict(box_bytes_grad=1000), dict(box_bytes_grad=1024), dict(box_bytes_cd=33792),
+                dict(box_bytes_cd=-2048), dict(chunk_len=3), dict(chunk_len=65)):
+        cfg = rc.rc_batch_config(*[int(dict(base, **bad).get(f, 0))
+                                   for f in rc.BATCH_CONFIG_FIELDS])
+        st, msg = _status("rc_batch_create", items, 1, C.byref(cfg), None, C.byref(out))
+        assert st == rc.RC_E_INVALID and "batch config" in msg, (bad, msg)

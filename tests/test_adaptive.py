@@ -104,14 +104,51 @@ def test_adaptive_c2_scale_sampled():
     assert g["stats"][0] < fixed["stats"][0]
 
 
+def test_adaptive_views_and_batches_equal_single_renders():
+    """Adaptive items through the persistent kernel: several views of one
+    volume (rc_render_views) and a batch mixing adaptive and fixed-step items
+    of three voxel types are bit-identical to one rc_render each."""
+    specs = [dict(seed=81, dtype=np.uint16, op="sobel3d", shading="blinn_phong", m=4, rng=40.0,
+                  ert=0.98, skip=True),
+             dict(seed=82, dtype=np.uint8, op="central", shading="none", m=3, rng=10.0, ert=0.0,
+                  skip=False),
+             dict(seed=83, dtype=np.float32, op="zucker_hummel", shading="blinn_phong", m=2,
+                  rng=0.05, ert=0.9, skip=True)]
+    items, refs = [], []
+    for sp in specs:
+        sc = W.config_small(seed=sp["seed"], dims=(41, 35, 30), dtype=sp["dtype"], image=(45, 37),
+                            op=sp["op"], shading=sp["shading"], ert=sp["ert"], skip=sp["skip"])
+        sc = _blocky(sc, np.random.default_rng(sp["seed"]))
+        vol = gpu_volume(sc, bricks=True)
+        tf = to_dev(sc.tf)
+        opt = dict(sc.options, adapt_factor=sp["m"], adapt_range=sp["rng"])
+        cams = [W.orbit_camera((41, 35, 30), sc.spacing, 31.0 * i, 25.0 - 7 * (i % 5),
+                               24 + 8 * (i % 3), 20 + 4 * (i % 4)) for i in range(18)]
+        auxes = [rc.new_aux(c) for c in cams]
+        outs = rc.rc_render_views(vol, cams, tf, sc.shading, opt, auxes=auxes)
+        for c, o, a in zip(cams, outs, auxes):
+            a1 = rc.new_aux(c)
+            ref = rc.rc_render(vol, c, tf, sc.shading, opt, aux=a1)
+            torch.cuda.synchronize()
+            assert torch.equal(o, ref) and torch.equal(a, a1)
+        for c, o in zip(cams[:3], outs[:3]):
+            for use_opt in (opt, sc.options):          # adaptive and fixed-step items
+                items.append({"vol": vol, "camera": c, "tf": tf, "shading": sc.shading,
+                              "options": use_opt, "out": torch.full_like(o, -1.0)})
+                refs.append(rc.rc_render(vol, c, tf, sc.shading, use_opt).clone())
+    rc.rc_render_batch(items)
+    torch.cuda.synchronize()
+    for it, ref in zip(items, refs):
+        assert torch.equal(it["out"], ref)
+
+
 def test_adaptive_rejected_where_unsupported():
+    """The reverse pass follows the fixed lattice: adaptive options are
+    refused there; adaptive sampling needs the brick ranges."""
     sc = W.config_small(seed=98, dims=(12, 12, 12), image=(8, 8), shading="none")
     vol = gpu_volume(sc, bricks=True)
     tf = to_dev(sc.tf)
     opt = dict(sc.options, adapt_factor=2, adapt_range=10.0)
-    with pytest.raises(rc.RCError) as e:
-        rc.rc_render_views(vol, sc.cameras, tf, sc.shading, opt)
-    assert e.value.status == rc.RC_E_UNSUPPORTED
     aux = rc.new_aux(sc.cameras[0])
     rc.rc_render(vol, sc.cameras[0], tf, sc.shading, opt, aux=aux)
     with pytest.raises(rc.RCError) as e:

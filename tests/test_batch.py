@@ -67,7 +67,13 @@ def _reference(items):
 
 @pytest.mark.parametrize("cfg", [None, dict(tile_w=16, waves_per_wg=4, wg_per_cu=2, order=0),
                                  dict(tile_w=4, waves_per_wg=2, wg_per_cu=1, order=1),
-                                 dict(tile_w=32, waves_per_wg=1, wg_per_cu=32, order=1)])
+                                 dict(tile_w=32, waves_per_wg=1, wg_per_cu=32, order=1),
+                                 # the smallest boxes and first chunks (chunks halve to fit)
+                                 dict(tile_w=8, waves_per_wg=1, wg_per_cu=8, order=1,
+                                      box_bytes_grad=2048, box_bytes_cd=2048, chunk_len=4),
+                                 # the largest boxes and first chunks
+                                 dict(tile_w=8, waves_per_wg=2, wg_per_cu=4, order=0,
+                                      box_bytes_grad=32768, box_bytes_cd=32768, chunk_len=64)])
 def test_batch_equals_single_renders(cfg):
     scenes = _scenes()
     items = _items(scenes)
@@ -144,12 +150,22 @@ def test_graph_replay_matches_eager():
 
 
 def test_autotune_and_cache(tmp_path):
+    """Launch shape, LDS box budgets and first chunk length are searched and
+    cached together (one JSON line per item set); a cache hit returns the
+    same configuration without timing."""
     items = _items(_scenes())
     path = str(tmp_path / "tune.jsonl")
     cfg = rc.rc_batch_autotune(items, path)
     assert cfg["tile_w"] in (4, 8, 16, 32) and cfg["wg_per_cu"] >= 1
+    # the scenes hold Sobel3D / Zucker-Hummel and central-difference items:
+    # both budgets are chosen
+    assert cfg["box_bytes_grad"] in (0, 8192, 12288, 16384, 20480)
+    assert cfg["box_bytes_cd"] in (0, 4096, 8192, 12288)
+    assert cfg["chunk_len"] in (0, 8, 32)
     lines = open(path).read().strip().splitlines()
-    assert len(lines) == 1 and json.loads(lines[0])["tile_w"] == cfg["tile_w"]
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert all(rec[k] == cfg[k] for k in cfg)
     cfg2 = rc.rc_batch_autotune(items, path)       # cache hit: no new line
     assert cfg2 == cfg and len(open(path).read().strip().splitlines()) == 1
     refs = _reference(items)
@@ -157,6 +173,15 @@ def test_autotune_and_cache(tmp_path):
     torch.cuda.synchronize()
     for it, (img, _) in zip(items, refs):
         assert torch.equal(it["out"], img)
+
+
+def test_batch_rejects_box_budget_beyond_the_workgroup():
+    """4 waves x 32 KiB boxes would need 128 KiB of LDS per workgroup."""
+    items = _items(_scenes()[:2])
+    with pytest.raises(rc.RCError) as e:
+        rc.rc_batch_create(items, dict(tile_w=8, waves_per_wg=4, wg_per_cu=2, order=0,
+                                       box_bytes_grad=32768, box_bytes_cd=32768))
+    assert e.value.status == rc.RC_E_INVALID and "64 KiB" in str(e.value)
 
 
 def test_batch_rejects_bad_item():

@@ -1,5 +1,6 @@
 """Reverse mode on the GPU vs the FP64 oracle adjoint and vs central finite
-differences of the oracle's forward (bar: relative error 1e-3)."""
+differences of the oracle's forward (bar: relative error 1e-3 per element,
+|gpu - ref| <= 1e-3 |ref| + 1e-5 max|ref|)."""
 import math
 
 import numpy as np
@@ -9,7 +10,7 @@ import torch
 import oracle
 import paper_1609_01317_amd as rc
 import workloads as W
-from tests.gpu_util import to_dev
+from tests.gpu_util import grad_excess, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -32,6 +33,15 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
 
 
+def _ok(gv, dv, gt, dt, label):
+    """Per-element bar on both gradients; prints the worst ratios."""
+    xv, rv = grad_excess(gv, dv)
+    xt, rt = grad_excess(gt, dt)
+    print(f"{label}: volume worst per-element ratio {xv:.3f} (max-normalised {rv:.2e}), "
+          f"tf {xt:.3f} ({rt:.2e})", flush=True)
+    return xv <= 1.0 and xt <= 1.0
+
+
 @pytest.mark.parametrize("seed,dtype,ert,nearest,ref",
                          [(31, np.float32, 0.0, False, 0.0), (32, np.float32, 0.9, False, 0.0),
                           (33, np.uint8, 0.0, False, 0.0), (34, np.uint16, 0.99, False, 0.0),
@@ -47,9 +57,8 @@ def test_adjoint_matches_oracle_small(seed, dtype, ert, nearest, ref):
     gv, gt = _gpu_grads(sc, cam, g)
     dv, dt = oracle.render_grad(oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax), cam,
                                 sc.tf, sc.options, g)
-    print(f"seed {seed}: rel err volume {_rel(gv, dv):.2e} tf {_rel(gt, dt):.2e}", flush=True)
     assert np.abs(dv).max() > 0 and np.abs(dt).max() > 0      # not a blank scene
-    assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
+    assert _ok(gv, dv, gt, dt, f"seed {seed}")
 
 
 @pytest.mark.parametrize("tf_len", [1024, 1025, 2048, 2049])
@@ -65,9 +74,8 @@ def test_adjoint_table_sizes(tf_len):
     gv, gt = _gpu_grads(sc, cam, g, tf=tf)
     dv, dt = oracle.render_grad(oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax), cam,
                                 tf, sc.options, g)
-    print(f"M {tf_len}: rel err volume {_rel(gv, dv):.2e} tf {_rel(gt, dt):.2e}", flush=True)
     assert np.abs(dv).max() > 0 and np.count_nonzero(dt) > 100
-    assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
+    assert _ok(gv, dv, gt, dt, f"M {tf_len}")
 
 
 SHADED = [
@@ -102,10 +110,8 @@ def test_shaded_adjoint_matches_oracle(case):
     gv, gt = gv.cpu().numpy().astype(np.float64), gt.cpu().numpy().astype(np.float64)
     dv, dt = oracle.render_grad(oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax), cam,
                                 sc.tf, sc.options, g, shading=sc.shading)
-    print(f"seed {case['seed']}: rel err volume {_rel(gv, dv):.2e} tf {_rel(gt, dt):.2e}",
-          flush=True)
     assert np.abs(dv).max() > 0 and np.abs(dt).max() > 0
-    assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
+    assert _ok(gv, dv, gt, dt, f"seed {case['seed']}")
 
 
 def test_autograd_function_matches_direct_calls():
@@ -143,8 +149,7 @@ def test_c5_views_match_oracle_adjoint(c5):
         gv, gt = _gpu_grads(sc, cam, g)
         dv, dt = oracle.render_grad(oracle.Volume(sc.volume, sc.spacing, 0, 1), cam, sc.tf,
                                     sc.options, g)
-        print(f"c5 view {vi}: rel err volume {_rel(gv, dv):.2e} tf {_rel(gt, dt):.2e}", flush=True)
-        assert _rel(gv, dv) <= REL and _rel(gt, dt) <= REL
+        assert _ok(gv, dv, gt, dt, f"c5 view {vi}")
 
 
 def _project(cam, p):
@@ -280,4 +285,48 @@ def test_render_views_fn_matches_oracle():
         a, b = oracle.render_grad(ov, c, sc.tf, sc.options, g[i])
         dv += a
         dt += b
-    assert _rel(vp.grad.cpu().numpy(), dv) <= REL and _rel(tp.grad.cpu().numpy(), dt) <= REL
+    assert _ok(vp.grad.cpu().numpy(), dv, tp.grad.cpu().numpy(), dt, "views fn")
+
+
+def test_c3_full_size_shaded_adjoint_sampled():
+    """Forward + backward at the benchmark's size: the 512^3 u16 phantom at
+    1024^2 with Sobel3D and Blinn-Phong (step 0.5, ERT 0.99), two orbit
+    views in one reverse launch.  dL/d(rgba) is seeded on 1500 pixels per
+    view and zero elsewhere, so dL/dvolume and dL/dtable come from those rays
+    only; both are compared per element with the FP64 oracle adjoint of the
+    same pixels."""
+    sc = W.config_c3(n_views=36)
+    opt = dict(sc.options, gradient_op="sobel3d")
+    vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+    rc.rc_build_bricks(vol, 8)
+    tf = to_dev(sc.tf)
+    cams = [sc.cameras[4], sc.cameras[22]]
+    rng = np.random.default_rng(606)
+    n_pix = 1024 * 1024
+    auxes = [rc.new_aux(c) for c in cams]
+    rc.rc_render_views(vol, cams, tf, sc.shading, opt, auxes=auxes)
+    grads, pix, gsub = [], [], []
+    for _ in cams:
+        p = rng.choice(n_pix, size=1500, replace=False)
+        g = np.zeros((n_pix, 4), dtype=np.float32)
+        g[p] = rng.normal(size=(1500, 4)).astype(np.float32)
+        grads.append(torch.from_numpy(g.reshape(1024, 1024, 4)).cuda())
+        pix.append(p)
+        gsub.append(g[p].astype(np.float64))
+    gv, gt = rc.rc_render_backward_views(vol, cams, tf, sc.shading, opt, auxes, grads)
+    torch.cuda.synchronize()
+    gv = gv.cpu().numpy()
+    gt = gt.cpu().numpy()
+    del vol
+    ov = oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
+    dv = np.zeros(sc.volume.shape)
+    dt = np.zeros(sc.tf.shape)
+    for c, p, g in zip(cams, pix, gsub):
+        a, b = oracle.render_grad(ov, c, sc.tf, opt, g, pixels=p, shading=sc.shading)
+        dv += a
+        dt += b
+    del ov
+    nz = int((dv != 0).sum())
+    print(f"c3 shaded adjoint: {nz} voxels with a gradient", flush=True)
+    assert nz > 10000 and np.count_nonzero(dt) > 50
+    assert _ok(gv, dv, gt, dt, "c3 shaded adjoint")

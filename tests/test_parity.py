@@ -161,7 +161,7 @@ def test_c2_full_frame():
 
 @pytest.mark.parametrize("op", ["central", "sobel3d", "zucker_hummel"])
 def test_c3_full_size_sampled(op, c3_scene):
-    """512^3 u16 -> 1024^2 in the benchmark's launch configuration, one
+    """512^3 u16 -> 1024^2 through rc_render (the single-image kernel), one
     view per operator, 20000 seeded pixels checked against the oracle."""
     sc = c3_scene
     vol = c3_scene.extra["gpu_volume"]
@@ -174,6 +174,79 @@ def test_c3_full_size_sampled(op, c3_scene):
     err, bad = compare(g["rgba"].reshape(-1, 4)[pix], r, opt["ert_threshold"])
     print(f"c3 {op}: max err {err:.3e}", flush=True)
     assert not bad.any()
+
+
+def _candidate_configs():
+    """The configurations the batch autotuner chooses among (its launch
+    shapes with default boxes; box budgets and first chunk lengths on two of
+    the shapes), plus the library's default: the images must not depend on
+    which one the benchmark picks."""
+    cfgs = [{"tile_w": 8, "waves_per_wg": 1, "wg_per_cu": 8, "order": 1}]
+    for tw in (4, 8, 16):
+        for w in (1, 4):
+            for pc in (4, 8, 16):
+                for od in (0, 1):
+                    cfgs.append({"tile_w": tw, "waves_per_wg": w, "wg_per_cu": max(1, pc // w),
+                                 "order": od})
+    for shape in ({"tile_w": 8, "waves_per_wg": 1, "wg_per_cu": 16, "order": 1},
+                  {"tile_w": 16, "waves_per_wg": 4, "wg_per_cu": 2, "order": 0}):
+        for g in (8192, 12288, 16384, 20480):
+            for d in (4096, 8192, 12288):
+                if max(g, d) * shape["waves_per_wg"] <= 65536:
+                    cfgs.append(dict(shape, box_bytes_grad=g, box_bytes_cd=d))
+        for n in (8, 32):
+            cfgs.append(dict(shape, chunk_len=n))
+    return cfgs
+
+
+def test_c3_benchmarked_launch_matches_oracle(c3_scene):
+    """The headline launch exactly as bench.py builds and times it: the
+    108-item render list (36 orbit views x central difference, Sobel3D,
+    Zucker-Hummel) in one persistent rc_batch with the autotuned launch
+    configuration.  4096 seeded pixels of every one of the 108 views are
+    checked against the FP64 oracle; then the same list rendered with every
+    candidate launch configuration gives bit-identical sampled pixels."""
+    import bench
+    import oracle
+
+    sc = c3_scene
+    vol = c3_scene.extra["gpu_volume"]
+    tf = to_dev(sc.tf)
+    _, all_items = bench.c3_render_list(sc, vol, tf)
+    cfg, batch = bench.c3_batch(all_items)
+    print(f"c3 batch: autotuned config {cfg}", flush=True)
+    rc.rc_batch_render(batch)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(404)
+    n_pix = 1024 * 1024
+    pix = [rng.choice(n_pix, size=4096, replace=False) for _ in all_items]
+    idx = [torch.from_numpy(p).cuda() for p in pix]
+
+    def gather():
+        return [it["out"].view(-1, 4).index_select(0, i).cpu().numpy()
+                for it, i in zip(all_items, idx)]
+
+    got = gather()
+    ov = oracle.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
+    worst = 0.0
+    content = 0
+    for v, it in enumerate(all_items):
+        r = oracle.render(ov, it["camera"], sc.tf, sc.shading, it["options"], pixels=pix[v])
+        err, bad = compare(got[v], r, it["options"]["ert_threshold"])
+        worst = max(worst, err)
+        content += int((r["rgba"][:, 3] > 1e-6).sum())
+        assert not bad.any(), (v, it["options"]["gradient_op"], int(bad.sum()), err)
+    print(f"c3 batch: 108 views x 4096 pixels, max err {worst:.3e}", flush=True)
+    assert content > 108 * 4096 // 4        # most sampled rays see the phantom
+    rc.rc_batch_destroy(batch)
+    for c in _candidate_configs():
+        b = rc.rc_batch_create(all_items, c)
+        rc.rc_batch_render(b)
+        torch.cuda.synchronize()
+        other = gather()
+        rc.rc_batch_destroy(b)
+        for v in range(len(all_items)):
+            assert np.array_equal(other[v], got[v]), (c, v)
 
 
 @pytest.fixture(scope="module")
