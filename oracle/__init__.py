@@ -94,7 +94,7 @@ def lib():
         L.orc_render_grad.restype = C.c_int
         L.orc_render_grad.argtypes = [C.POINTER(_Volume), C.POINTER(_Camera), dp, C.c_int,
                                       C.POINTER(_Shading), C.POINTER(_Options), lp, C.c_long,
-                                      dp, dp, dp]
+                                      dp, dp, dp, dp]
         L.orc_render_surface.restype = C.c_int
         L.orc_render_surface.argtypes = [C.POINTER(_Volume), C.POINTER(_Camera), dp, C.c_int,
                                          C.POINTER(_Shading), C.POINTER(_SurfaceOptions), lp,
@@ -212,8 +212,13 @@ def render(vol: Volume, cam, tf, shading, options, pixels=None, threads=0):
     return out
 
 
-def render_grad(vol: Volume, cam, tf, options, g_rgba, pixels=None, shading=None):
-    """dL/dvolume [nz,ny,nx] and dL/dTF [M,4]; shading None means NONE."""
+def render_grad(vol: Volume, cam, tf, options, g_rgba, pixels=None, shading=None,
+                abs_sum=False):
+    """dL/dvolume [nz,ny,nx] and dL/dTF [M,4]; shading None means NONE.
+
+    With abs_sum, a third array [nz,ny,nx]: per voxel, the sum of the
+    magnitudes of the terms that make up its dL/dvolume entry (how much
+    cancellation the entry carries)."""
     L = lib()
     c, o = _camera(cam), _options(options)
     s = C.byref(_shading(shading)) if shading is not None else None
@@ -227,11 +232,12 @@ def render_grad(vol: Volume, cam, tf, options, g_rgba, pixels=None, shading=None
     assert g.shape[0] == n
     dvol = np.zeros(vol.data.shape)
     dtf = np.zeros(t.shape)
+    dabs = np.zeros(vol.data.shape) if abs_sum else None
     rc = L.orc_render_grad(C.byref(vol.s), C.byref(c), _dp(t), t.shape[0], s, C.byref(o), pix_p,
-                           n, _dp(g), _dp(dvol), _dp(dtf))
+                           n, _dp(g), _dp(dvol), _dp(dtf), _dp(dabs) if abs_sum else None)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
-    return dvol, dtf
+    return (dvol, dtf, dabs) if abs_sum else (dvol, dtf)
 
 
 def _surface_options(opt):

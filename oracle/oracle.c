@@ -555,8 +555,11 @@ int orc_render(const orc_volume* v, const orc_camera* cam, const double* tf, int
 /* continues through the TF interpolation to u, through the clamp to    */
 /* the value, and through the trilinear weights to the 8 voxels.        */
 /* ------------------------------------------------------------------ */
-/* Trilinear weights of p (Section 3.4) scattered: dvol[corner] += w * s. */
-static void scatter_trilinear(const orc_volume* v, const double p[3], double s, double* dvol) {
+/* Trilinear weights of p (Section 3.4) scattered: dvol[corner] += w * s.
+ * With dabs, |w * s| is summed there as well: the magnitude of the terms
+ * whose sum is dvol, i.e. how much cancellation each entry carries. */
+static void scatter_trilinear(const orc_volume* v, const double p[3], double s, double* dvol,
+                              double* dabs) {
     double fx0 = floor(p[0]), fy0 = floor(p[1]), fz0 = floor(p[2]);
     double tx = p[0] - fx0, ty = p[1] - fy0, tz = p[2] - fz0;
     for (int c = 0; c < 8; ++c) {
@@ -564,7 +567,9 @@ static void scatter_trilinear(const orc_volume* v, const double p[3], double s, 
         double w = (cx ? tx : 1 - tx) * (cy ? ty : 1 - ty) * (cz ? tz : 1 - tz);
         long ii = clampl((long)fx0 + cx, v->nx), jj = clampl((long)fy0 + cy, v->ny),
              kk = clampl((long)fz0 + cz, v->nz);
-        dvol[(kk * (long)v->ny + jj) * (long)v->nx + ii] += w * s;
+        long at = (kk * (long)v->ny + jj) * (long)v->nx + ii;
+        dvol[at] += w * s;
+        if (dabs) dabs[at] += fabs(w * s);
     }
 }
 
@@ -572,7 +577,7 @@ static void scatter_trilinear(const orc_volume* v, const double p[3], double s, 
  * so dL/dG_a scatters through each tap's trilinear weights, scaled like
  * the forward (mask weight / gain / spacing / value range). */
 static void gradient_adjoint(const orc_volume* v, int op, const double p[3], const double dg[3],
-                             double* dvol) {
+                             double* dvol, double* dabs) {
     for (int a = 0; a < 3; ++a) {
         if (dg[a] == 0.0) continue;
         double s = dg[a] / op_gain(op) / v->spacing[a] / (v->vmax - v->vmin);
@@ -587,8 +592,8 @@ static void gradient_adjoint(const orc_volume* v, int op, const double p[3], con
                 memcpy(q0, q1, sizeof q0);
                 q1[a] += 1.0;
                 q0[a] -= 1.0;
-                scatter_trilinear(v, q1, w * s, dvol);
-                scatter_trilinear(v, q0, -w * s, dvol);
+                scatter_trilinear(v, q1, w * s, dvol, dabs);
+                scatter_trilinear(v, q0, -w * s, dvol, dabs);
             }
     }
 }
@@ -649,7 +654,7 @@ static void shade_adjoint(const orc_shading* sh, const double rgb[3], const doub
 
 int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
                     const orc_shading* sh_in, const orc_options* opt, const long* pix, long n,
-                    const double* g_rgba, double* dvol, double* dtf) {
+                    const double* g_rgba, double* dvol, double* dtf, double* dvol_abs) {
     if (check_args(v, cam, tf, M, opt) || !g_rgba || !dvol || !dtf) return -1;
     if (opt->adapt_factor > 1) return -1;      /* the reverse mode follows the fixed lattice */
     orc_shading none;
@@ -728,9 +733,10 @@ int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf
             }
             /* the value: through the clamp to the trilinear (or nearest) weights */
             if (s->interior)
-                scatter_trilinear(v, pr, du * (double)(M - 1) / (v->vmax - v->vmin), dvol);
+                scatter_trilinear(v, pr, du * (double)(M - 1) / (v->vmax - v->vmin), dvol,
+                                  dvol_abs);
             /* the gradient operator's taps */
-            gradient_adjoint(v, opt->gradient_op, pr, dG, dvol);
+            gradient_adjoint(v, opt->gradient_op, pr, dG, dvol, dvol_abs);
             for (int ch = 0; ch < 3; ++ch) B[ch] = a * s->c[ch] + (1.0 - a) * B[ch];
             P *= (1.0 - a);
         }

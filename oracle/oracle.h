@@ -128,13 +128,17 @@ int orc_render(const orc_volume* v, const orc_camera* cam, const double* tf, int
  * Reverse mode of orc_render.  sh = NULL means shading NONE; with a shading
  * model the chain also runs through the lighting, the normalisation and the
  * gradient operator's taps.  g_rgba[n*4] = dL/d(rgba) of the listed pixels.
- * dvol[nz*ny*nx] and dtf[M*4] are accumulated (+=).  Uses the same lattice
+ * dvol[nz*ny*nx] and dtf[M*4] are accumulated (+=).  dvol_abs (NULL or
+ * [nz*ny*nx], accumulated) receives the sum of the magnitudes of the terms
+ * added into each dvol entry: an entry whose terms cancel has
+ * dvol_abs >> |dvol|, and a finite-precision sum of those terms can only be
+ * trusted to a few units of rounding times dvol_abs.  Uses the same lattice
  * (primary sample count) and the same early ray termination as orc_render.
  * Returns 0, or -1 on bad arguments.
  */
 int orc_render_grad(const orc_volume* v, const orc_camera* cam, const double* tf, int M,
                     const orc_shading* sh, const orc_options* opt, const long* pix, long n,
-                    const double* g_rgba, double* dvol, double* dtf);
+                    const double* g_rgba, double* dvol, double* dtf, double* dvol_abs);
 
 /* First-hit surface mode (Sections 3, 3.11 and 5.1). */
 typedef struct {

@@ -47,11 +47,12 @@ int main(void) {
     double* thit = malloc(sizeof(double) * n);
     double* g = malloc(sizeof(double) * n * 4);
     double* dvol = calloc((size_t)NX * NY * NZ, sizeof(double));
+    double* dabs = calloc((size_t)NX * NY * NZ, sizeof(double));
     double* dtf = calloc((size_t)M * 4, sizeof(double));
     int* flags = malloc(sizeof(int) * n);
     int* kl = malloc(sizeof(int) * n);
     long pix[5] = {0, 7, 64, 65, n - 1};
-    if (!rgba || !alt || !tfin || !thit || !g || !dvol || !dtf || !flags || !kl) return 2;
+    if (!rgba || !alt || !tfin || !thit || !g || !dvol || !dabs || !dtf || !flags || !kl) return 2;
     for (long i = 0; i < n * 4; ++i) g[i] = sin(0.37 * (double)i);
     int calls = 0;
     for (int c = 0; c < 2; ++c)
@@ -77,9 +78,10 @@ int main(void) {
                     if (variant != 3) {     /* the reverse mode has no adaptive sampling */
                         if (orc_render_grad(&v, &cams[c], tf, M,
                                             model == ORC_SHADE_NONE ? NULL : &sh, &o, NULL, n, g,
-                                            dvol, dtf) != 0)
+                                            dvol, dtf, (c & 1) ? dabs : NULL) != 0)
                             return 6;
-                        if (!finite_all(dvol, (long)NX * NY * NZ) || !finite_all(dtf, M * 4))
+                        if (!finite_all(dvol, (long)NX * NY * NZ) || !finite_all(dtf, M * 4) ||
+                            !finite_all(dabs, (long)NX * NY * NZ))
                             return 7;
                     }
                     orc_surface_options so = {1.0, op, 60.0, 200.0, 6,
@@ -97,6 +99,6 @@ int main(void) {
         return 10;
     printf("sanitize_check: %d oracle calls ok\n", calls);
     free(data); free(tf); free(rgba); free(alt); free(tfin); free(thit); free(g);
-    free(dvol); free(dtf); free(flags); free(kl);
+    free(dvol); free(dabs); free(dtf); free(flags); free(kl);
     return 0;
 }

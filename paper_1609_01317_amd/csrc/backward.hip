@@ -6,7 +6,7 @@
 // transmittance written to rc_aux.
 #include <cmath>
 
-#include "march.h"
+#include "stencil.h"
 
 namespace rc {
 
@@ -128,7 +128,7 @@ __device__ __forceinline__ void bwd_finish(const RenderParams& P, const float4* 
     }
     S.c[0] = S.rgba.x; S.c[1] = S.rgba.y; S.c[2] = S.rgba.z;
     if (LIT && lit) {
-        gradient<VT, OP, true>(P, base, S.ox, S.oy, S.oz, S.C, S.g, corner);
+        gradient_exact<VT, OP>(P, base, S.ox, S.oy, S.oz, S.C, S.g);
         shade(P, S.rgba, S.g, S.pv, rs, S.c);
     }
 }
@@ -239,8 +239,10 @@ __device__ __forceinline__ void shade_adjoint(const RenderParams& P, const BwdSa
     }
 }
 
-// Reverse of gradient<VT, OP>: the separable 4x4x4 filters transposed.  A
-// footprint voxel (x, y, z) carries, for dL/dG = (gx, gy, gz) in scaled units,
+// Reverse of the gradient operator (gradient, gradient_exact: the same
+// linear map of the footprint's voxels), as its separable 4x4x4 filters
+// transposed.  A footprint voxel (x, y, z) carries, for dL/dG = (gx, gy, gz)
+// in scaled units,
 //   gx (D'x A'y A'z + gamma D'x Ly Lz) + gy (A'x D'y A'z + gamma Lx D'y Lz)
 //   + gz (A'x A'y D'z + gamma Lx Ly D'z),
 // added to the clamped voxel of the linear gradient array.

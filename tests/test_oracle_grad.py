@@ -149,3 +149,31 @@ def test_shaded_grad_tf_matches_fd(orc, model, op, nearest):
             tm[i, ch] -= h
             fd = (_loss_sh(orc, sc.volume, sc, tp, g) - _loss_sh(orc, sc.volume, sc, tm, g)) / (2 * h)
             assert abs(fd - dtf[i, ch]) <= 1e-6 * max(1.0, abs(fd)), (i, ch, fd, dtf[i, ch])
+
+
+def test_abs_sum_is_the_sum_of_term_magnitudes(orc):
+    """The oracle's optional cancellation measure: per voxel, the sum of the
+    magnitudes of the terms added into dL/dvolume.  It leaves dL/dvolume
+    unchanged, bounds |dL/dvolume|, adds up over pixels (a sum of
+    magnitudes, not the magnitude of a sum: some voxels cancel), is even in
+    g and scales with |g|."""
+    sc = W.config_small(seed=32, dims=(9, 8, 7), dtype=np.uint8, image=(6, 5), op="sobel3d")
+    rng = np.random.default_rng(32)
+    H, Wd = sc.cameras[0]["height"], sc.cameras[0]["width"]
+    g = rng.normal(size=(H * Wd, 4))
+    v = orc.Volume(sc.volume, sc.spacing, sc.vmin, sc.vmax)
+    dv0, dt0 = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, g, shading=sc.shading)
+    dv, dt, ab = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, g, shading=sc.shading,
+                                 abs_sum=True)
+    assert np.array_equal(dv, dv0) and np.array_equal(dt, dt0)
+    assert (ab >= np.abs(dv) * (1 - 1e-12)).all()
+    assert (ab[dv != 0] > 0).all() and (ab > 2 * np.abs(dv) + 1e-12).any()
+    per_pixel = np.zeros_like(ab)
+    for p in range(H * Wd):
+        _, _, a = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, g[p:p + 1], pixels=[p],
+                                  shading=sc.shading, abs_sum=True)
+        per_pixel += a
+    assert np.allclose(per_pixel, ab, rtol=1e-12, atol=0)
+    _, _, a_neg = orc.render_grad(v, sc.cameras[0], sc.tf, sc.options, -2.0 * g,
+                                  shading=sc.shading, abs_sum=True)
+    assert np.allclose(a_neg, 2.0 * ab, rtol=1e-12, atol=0)
