@@ -21,7 +21,7 @@ __all__ = [
     "Batch", "rc_batch_create", "rc_batch_render", "rc_batch_destroy", "rc_render_batch",
     "rc_batch_autotune", "rc_render_views", "rc_render_backward_views", "RenderViewsFn",
     "rc_render_surface", "surface_options_struct", "rc_debug_bounds_violations",
-    "rc_debug_bounds_reset",
+    "rc_debug_bounds_reset", "rc_render_views_noalloc", "NOALLOC_SCRATCH_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -150,6 +150,8 @@ def _L():
         L.rc_render_views.restype = C.c_int
         L.rc_render_views.argtypes = [vp, C.POINTER(rc_camera), C.c_int, vp, C.c_int,
                                       C.POINTER(rc_shading), C.POINTER(rc_options), pp, pp, vp]
+        L.rc_render_views_noalloc.restype = C.c_int
+        L.rc_render_views_noalloc.argtypes = L.rc_render_views.argtypes
         L.rc_render_backward_views.restype = C.c_int
         L.rc_render_backward_views.argtypes = [vp, C.POINTER(rc_camera), C.c_int, vp, C.c_int,
                                                C.POINTER(rc_shading), C.POINTER(rc_options), pp,
@@ -466,6 +468,20 @@ def rc_render_views(vol: Volume, cameras, tf: torch.Tensor, shading: dict, optio
     list of [H,W,4] outputs."""
     return _render_views("rc_render_views", vol, cameras, tf, shading, options, outs, auxes,
                          stream)
+
+
+# size of the library's fixed scratch array (RC_NOALLOC_SCRATCH_BYTES in rc.h)
+NOALLOC_SCRATCH_BYTES = 4 << 20
+
+
+def rc_render_views_noalloc(vol: Volume, cameras, tf: torch.Tensor, shading: dict,
+                            options: dict, outs, auxes=None, stream=None):
+    """rc_render_views with the library's fixed scratch array instead of any
+    device allocation; `outs` (and `auxes`) must be supplied by the caller."""
+    if outs is None:
+        raise ValueError("rc_render_views_noalloc: the caller supplies the outputs")
+    return _render_views("rc_render_views_noalloc", vol, cameras, tf, shading, options, outs,
+                         auxes, stream)
 
 
 def _render_views(fn, vol, cameras, tf, shading, options, outs, auxes, stream):

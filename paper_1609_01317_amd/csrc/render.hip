@@ -611,3 +611,51 @@ extern "C" rc_status rc_render_views(const rc_volume* v, const rc_camera* cams, 
     if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
     return st;
 }
+
+// ---------------------------------------------------------------- allocation-free views
+// rc_render_views' scratch in a fixed device array instead of a
+// stream-ordered allocation.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is looked up once per
+// device (hipGetSymbolAddress, with that device current) and only that
+// address is ever passed to kernels.
+static __device__ __align__(256) unsigned char scratch[RC_NOALLOC_SCRATCH_BYTES];
+static std::atomic<char*> g_scratch_dev[64];
+
+static rc_status noalloc_scratch(char** out) {
+    int dev = -1;
+    RC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        return fail(RC_E_UNSUPPORTED, "rc_render_views_noalloc: device %d (at most 64 devices)", dev);
+    char* p = g_scratch_dev[dev].load(std::memory_order_acquire);
+    if (!p) {
+        void* q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        // threads racing here store the same address
+        p = (char*)q;
+        g_scratch_dev[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return RC_OK;
+}
+
+extern "C" rc_status rc_render_views_noalloc(const rc_volume* v, const rc_camera* cams,
+                                             int n_views, const float* tf_rgba_dev, int tf_len,
+                                             const rc_shading* sh, const rc_options* opt,
+                                             float* const* out_rgba, rc_aux* const* aux,
+                                             void* stream) {
+    rc_status st = check_views_args(v, cams, n_views, tf_rgba_dev, tf_len, sh, opt, out_rgba,
+                                    "rc_render_views_noalloc");
+    if (st != RC_OK) return st;
+    const size_t need = views_scratch_bytes(v, tf_len, opt);
+    if (need > (size_t)RC_NOALLOC_SCRATCH_BYTES)
+        return fail(RC_E_INVALID,
+                    "rc_render_views_noalloc: this call needs %zu bytes of scratch, more than the "
+                    "%u the library holds (fewer bricks or table entries, or rc_render_views)",
+                    need, (unsigned)RC_NOALLOC_SCRATCH_BYTES);
+    char* sp = nullptr;
+    st = noalloc_scratch(&sp);
+    if (st != RC_OK) return st;
+    return render_views_into(v, cams, n_views, tf_rgba_dev, tf_len, sh, opt, out_rgba, aux, sp,
+                             (hipStream_t)stream);
+}

@@ -136,3 +136,10 @@ def test_batch_config_rejected_on_host():
                                    for f in rc.BATCH_CONFIG_FIELDS])
         st, msg = _status("rc_batch_create", items, 1, C.byref(cfg), None, C.byref(out))
         assert st == rc.RC_E_INVALID and "batch config" in msg, (bad, msg)
+
+
+def test_noalloc_scratch_size_matches_header():
+    src = open(os.path.join(ROOT, "include", "rc.h")).read()
+    m = re.search(r"#define\s+RC_NOALLOC_SCRATCH_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", src)
+    assert m, "RC_NOALLOC_SCRATCH_BYTES not found"
+    assert rc.NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))
