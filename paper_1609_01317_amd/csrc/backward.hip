@@ -4,6 +4,7 @@
 // shading model is on.  No per-sample state is stored by the forward pass; the
 // transmittance in front of each sample is recovered from the final
 // transmittance written to rc_aux.
+#include <algorithm>
 #include <cmath>
 
 #include "stencil.h"
@@ -17,12 +18,24 @@ struct BackwardParams {
     int lds_table;          // 1: read the table from an LDS copy
     int M4;                 // table entries * 4 (the dTF length)
     unsigned int* dbg;      // bounds-checked build: violation counter; else null
+    int box_floats;         // LDS dV box of the chunked kernel (voxels); 0 = per-ray kernel
+    int chunk_len;          // first chunk length of the chunked kernel, lattice steps
 };
 
 constexpr int kBwdTile = 8;               // 8x8 pixels, one wave per workgroup
 constexpr int kBwdLdsEntries = 2048;      // table sizes up to this are privatised in LDS
 constexpr int kBwdLdsTable = 1024;        // and up to this also read from LDS
 constexpr float kTinyT = 1e-30f;
+// The chunked kernel: blocks of kBwdBoxWaves waves (one tile each) share
+// the table gradient in LDS -- tables up to kBwdBoxTfEntries entries, so a
+// whole block's samples, which mostly read a few hot entries, meet in LDS
+// instead of at a few device addresses -- and each wave has a dV box of up
+// to kBwdBoxFloats voxels in what the 160 KiB of LDS leave.
+constexpr int kBwdBoxWaves = 8;
+constexpr int kBwdBoxTfEntries = 4096;
+constexpr int kBwdBoxFloats = 4096;
+constexpr int kBwdLdsBytes = 160 * 1024;
+constexpr int kBwdChunk = 16;             // first chunk length in lattice steps
 
 __device__ __forceinline__ void add_dtf(const BackwardParams& B, float* lds, int i, int ch, float v) {
     if (v == 0.0f) return;
@@ -142,6 +155,30 @@ __device__ __forceinline__ void bwd_sample(const RenderParams& P, const float4* 
     bwd_finish<VT, OP, LIT>(P, tab, rs, lit, corner, S);
 }
 
+// Where volume-gradient contributions go: straight to dV in device memory
+// (lds == null), or to a chunk's voxel box in LDS (the box covers every
+// voxel the chunk's samples reach, clamped indices included), which is
+// added to dV once per chunk (dv_box_flush).
+struct DvSink {
+    float* lds;             // box [dim2][dim1][dim0] or null
+    int lo[3];              // voxel index of box voxel (0, 0, 0)
+    int bx, bxy, n;         // row and slab strides, voxels in the box
+};
+
+__device__ __forceinline__ void dv_atomic(const RenderParams& P, const BackwardParams& B,
+                                          const DvSink& sk, int x, int y, int z, float w) {
+    if (sk.lds) {
+        atomicAdd(&sk.lds[RC_IDX(P.dbg, (z - sk.lo[2]) * sk.bxy + (y - sk.lo[1]) * sk.bx +
+                                             (x - sk.lo[0]),
+                                 sk.n)],
+                  w);
+    } else {
+        unsafeAtomicAdd(&B.dvol[RC_IDX(P.dbg, ((long long)z * P.ny + y) * P.nx + x,
+                                       (long long)P.nx * P.ny * P.nz)],
+                        w);
+    }
+}
+
 // A ray's volume-gradient contributions to the 8 corners of one cell,
 // summed while its samples stay in that cell (at half-voxel steps most
 // cells hold two or more consecutive samples) and added to dV when the ray
@@ -151,7 +188,8 @@ struct DvRun {
     float w[8];                     // corner (x + 2y + 4z) contributions
 };
 
-__device__ __forceinline__ void dv_flush(const RenderParams& P, const BackwardParams& B, DvRun& r) {
+__device__ __forceinline__ void dv_flush(const RenderParams& P, const BackwardParams& B,
+                                         const DvSink& sk, DvRun& r) {
     if (r.c[0] == INT_MIN) return;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -159,17 +197,15 @@ __device__ __forceinline__ void dv_flush(const RenderParams& P, const BackwardPa
         int x = clampi(r.c[0] + (q & 1), 0, P.nx - 1);
         int y = clampi(r.c[1] + ((q >> 1) & 1), 0, P.ny - 1);
         int z = clampi(r.c[2] + (q >> 2), 0, P.nz - 1);
-        unsafeAtomicAdd(&B.dvol[RC_IDX(P.dbg, ((long long)z * P.ny + y) * P.nx + x,
-                                       (long long)P.nx * P.ny * P.nz)],
-                        r.w[q]);
+        dv_atomic(P, B, sk, x, y, z, r.w[q]);
     }
     r.c[0] = INT_MIN;
 }
 
-__device__ __forceinline__ void dv_add(const RenderParams& P, const BackwardParams& B, DvRun& r,
-                                       const Cell& C, float dv) {
+__device__ __forceinline__ void dv_add(const RenderParams& P, const BackwardParams& B,
+                                       const DvSink& sk, DvRun& r, const Cell& C, float dv) {
     if (C.c[0] != r.c[0] || C.c[1] != r.c[1] || C.c[2] != r.c[2]) {
-        dv_flush(P, B, r);
+        dv_flush(P, B, sk, r);
         r.c[0] = C.c[0]; r.c[1] = C.c[1]; r.c[2] = C.c[2];
 #pragma unroll
         for (int q = 0; q < 8; ++q) r.w[q] = 0.0f;
@@ -248,7 +284,8 @@ __device__ __forceinline__ void shade_adjoint(const RenderParams& P, const BwdSa
 // added to the clamped voxel of the linear gradient array.
 template <int OP>
 __device__ __forceinline__ void gradient_adjoint(const RenderParams& P, const BackwardParams& Bp,
-                                                 const Cell& C, const float dg[3]) {
+                                                 const DvSink& sk, const Cell& C,
+                                                 const float dg[3]) {
     constexpr bool SEP = OpTaps<OP>::kSep;
     const float gm = OpTaps<OP>::gamma;
     const float gx = dg[0] * P.gscale[0], gy = dg[1] * P.gscale[1], gz = dg[2] * P.gscale[2];
@@ -272,16 +309,12 @@ __device__ __forceinline__ void gradient_adjoint(const RenderParams& P, const Ba
             const float fxA = SEP ? ky.A[y] * kz.A[z] : 0.0f, fxL = gm * ky.L[y] * kz.L[z];
             const float fyA = SEP ? ky.D[y] * kz.A[z] : 0.0f, fyL = gm * ky.D[y] * kz.L[z];
             const float fzA = SEP ? ky.A[y] * kz.D[z] : 0.0f, fzL = gm * ky.L[y] * kz.D[z];
-            const long long row = ((long long)zi[z] * P.ny + yi[y]) * P.nx;
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
                 float w = gx * kx.D[x] * (fxA + fxL);
                 w = fmaf(gy, fmaf(kx.A[x], fyA, kx.L[x] * fyL), w);
                 w = fmaf(gz, fmaf(kx.A[x], fzA, kx.L[x] * fzL), w);
-                if (w != 0.0f)
-                    unsafeAtomicAdd(&Bp.dvol[RC_IDX(P.dbg, row + xi[x],
-                                                    (long long)P.nx * P.ny * P.nz)],
-                                    w);
+                if (w != 0.0f) dv_atomic(P, Bp, sk, xi[x], yi[y], zi[z], w);
             }
         }
 }
@@ -298,7 +331,8 @@ __device__ __forceinline__ void gradient_adjoint(const RenderParams& P, const Ba
 template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const BackwardParams& Bp,
                                                float* lds, DtfRun& run, DvRun& vrun,
-                                               const BwdSample& S, const RayShade& rs,
+                                               const DvSink& sk, const BwdSample& S,
+                                               const RayShade& rs,
                                                float Tk, const float4& g, const float Bk1[3],
                                                float Pk1) {
     float ta = Tk * S.a;
@@ -310,14 +344,14 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
     float w0 = 1.0f - S.t, w1 = S.t;
     const float d4[4] = {drgb[0], drgb[1], drgb[2], da};
     dtf_add(P, Bp, lds, run, S.i, w0, w1, d4);
-    if (LIT) gradient_adjoint<OP>(P, Bp, S.C, dg);
+    if (LIT) gradient_adjoint<OP>(P, Bp, sk, S.C, dg);
     if (!(S.vn > 0.0f && S.vn < 1.0f)) return;      // clamped: no dependence on the value
     float du = drgb[0] * (S.e1.x - S.e0.x) + drgb[1] * (S.e1.y - S.e0.y) +
                drgb[2] * (S.e1.z - S.e0.z) + da * (S.e1.w - S.e0.w);
     float dv = du * P.Mm1 * P.inv_range;
     if (dv == 0.0f) return;
     // nearest sampling has fraction 0: only corner 0 gets a non-zero weight
-    dv_add(P, Bp, vrun, S.C, dv);
+    dv_add(P, Bp, sk, vrun, S.C, dv);
 }
 
 // One workgroup = one wave = one 8x8 pixel tile of one view (work order:
@@ -385,6 +419,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
             float corner[8], cn[8];
             DtfRun run;
             DvRun vrun;
+            const DvSink glob{nullptr, {0, 0, 0}, 0, 0, 0};
             bwd_fetch<VT>(P, R, last, S, corner);
             bwd_finish<VT, OP, LIT>(P, tab, rs, true, corner, S);
             for (int k = last; k >= 0; --k) {
@@ -393,7 +428,8 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                 if (k < anchor) {
                     Q *= om;
                     float Tk = Q > 0.0f ? Ta / Q : 0.0f;
-                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, vrun, S, rs, Tk, g, Bk1, Pk1);
+                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, vrun, glob, S, rs, Tk, g, Bk1,
+                                                Pk1);
                 }
                 Bk1[0] = fmaf(S.a, S.c[0], om * Bk1[0]);
                 Bk1[1] = fmaf(S.a, S.c[1], om * Bk1[1]);
@@ -406,7 +442,7 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
                 }
             }
             dtf_flush(P, Bp, lds, run);
-            dv_flush(P, Bp, vrun);
+            dv_flush(P, Bp, glob, vrun);
         }
     }
     if (Bp.lds_tf) {
@@ -418,19 +454,244 @@ raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
     }
 }
 
+
+// Maximum of non-negative doubles over the wave, exact: their bit patterns
+// order like unsigned 64-bit integers (0 is the identity for lanes a DPP
+// move does not write).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64_or0(unsigned long long v) {
+    unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWS, 0xF, false);
+    unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWS, 0xF, false);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ double wave_max_nonneg(double x) {
+    unsigned long long v = (unsigned long long)__double_as_longlong(x);
+    v = max(v, dpp_u64_or0<0xB1, 0xF>(v));     // quad_perm 1,0,3,2
+    v = max(v, dpp_u64_or0<0x4E, 0xF>(v));     // quad_perm 2,3,0,1
+    v = max(v, dpp_u64_or0<0x141, 0xF>(v));    // row_half_mirror
+    v = max(v, dpp_u64_or0<0x140, 0xF>(v));    // row_mirror
+    v = max(v, dpp_u64_or0<0x142, 0xA>(v));    // row_bcast:15
+    v = max(v, dpp_u64_or0<0x143, 0xC>(v));    // row_bcast:31
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Add a chunk's dV box to dV and clear it.  Lane i reads box entries i,
+// i + 64, ...; box coordinates advance incrementally (no divisions).
+__device__ __forceinline__ void dv_box_flush(const RenderParams& P, const BackwardParams& B,
+                                             const DvSink& sk, int lane) {
+    const int bx = sk.bx, by = sk.bxy / sk.bx;
+    int x = lane % bx, y = (lane / bx) % by, z = lane / sk.bxy;
+    const int step_x = 64 % bx, step_y = 64 / bx;
+    for (int i = lane; i < sk.n; i += 64) {
+        const float w = sk.lds[i];
+        if (w != 0.0f) {
+            const int gx = sk.lo[0] + x, gy = sk.lo[1] + y, gz = sk.lo[2] + z;
+            // taps are clamped into the grid: entries outside it stay 0
+            if (gx >= 0 && gy >= 0 && gz >= 0 && gx < P.nx && gy < P.ny && gz < P.nz)
+                unsafeAtomicAdd(&B.dvol[RC_IDX(P.dbg, ((long long)gz * P.ny + gy) * P.nx + gx,
+                                               (long long)P.nx * P.ny * P.nz)],
+                                w);
+            sk.lds[i] = 0.0f;
+        }
+        x += step_x;
+        y += step_y;
+        if (x >= bx) { x -= bx; ++y; }
+        while (y >= by) { y -= by; ++z; }
+    }
+}
+
+// The reverse march in chunks shared by the wave, for renders whose samples
+// scatter many contributions (the shaded reverse: up to 64 voxels per
+// sample through the operator's taps).  Each lane still runs its own ray
+// back to front; the wave only agrees on a window of ray parameter
+// (thi - len step, thi], thi = the latest pending sample of any lane, and
+// every lane processes its samples inside it.  Their contributions to dV go
+// to an LDS box over the window's voxels (LDS atomics), which is added to
+// dV once per chunk: one device atomic per touched voxel instead of one per
+// tap and sample.  A window whose box does not fit even at 2 steps sends
+// its contributions straight to dV.  Same work order and per-ray arithmetic
+// as raycast_bwd.
+template <typename VT, int OP, bool LIT>
+__global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParams P, ViewSet S,
+                                                                    BackwardParams Bp) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float4* tab = P.tf;
+    // LDS: the block's table gradient (shared by its waves), the table copy,
+    // then one dV box per wave
+    const int tf_floats = (Bp.lds_tf ? P.M * 4 : 0) + (Bp.lds_table ? P.M * 4 : 0);
+    float* dvb = lds + tf_floats + wave * Bp.box_floats;
+    if (Bp.lds_tf)
+        for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) lds[i] = 0.0f;
+    if (Bp.lds_table) {
+        float4* t = (float4*)(lds + (Bp.lds_tf ? P.M * 4 : 0));
+        for (int i = threadIdx.x; i < P.M; i += blockDim.x) t[i] = P.tf[i];
+        tab = t;
+    }
+    for (int i = lane; i < Bp.box_floats; i += 64) dvb[i] = 0.0f;
+    __syncthreads();
+    // one tile per wave, in the work order of raycast_bwd
+    int b = 0, v = view_of_unit(S, 1, (int)blockIdx.x * kBwdBoxWaves + wave, b);
+    const ViewParams& V = S.v[v < 0 ? 0 : v];
+    int tiles_x = (V.W + kBwdTile - 1) / kBwdTile, tiles_y = (V.H + kBwdTile - 1) / kBwdTile;
+    int tx = centre_out(b % tiles_x, tiles_x), ty = centre_out(b / tiles_x, tiles_y);
+    int px = tx * kBwdTile + (lane % kBwdTile);
+    int py = ty * kBwdTile + (lane / kBwdTile);
+    const bool valid = v >= 0 && b < tiles_x * tiles_y && px < V.W && py < V.H;
+    Ray R;
+    R.K = -1;
+    R.t_in = R.t_out = 0.0;
+    for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = R.p0[a] = R.dp[a] = 0.0;
+    if (valid) setup_ray(P, V, px, py, R);
+    RayShade rs;
+    ray_shade(P, R, rs);
+    rc_aux ax{-1, 0.0f};
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+        long long pix = (long long)py * V.W + px;
+        ax = V.aux[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
+        g = V.grad[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
+    }
+    const int last = ax.k_last;
+    const bool has = valid && R.K >= 0 && last >= 0 && last <= R.K;
+    // Anchor: the last index a whose front transmittance T_a is at least
+    // kTinyT (see raycast_bwd).
+    int anchor = last + 1;
+    float Ta = ax.t_final;
+    if (has && !(Ta >= kTinyT)) {
+        float T = 1.0f;
+        anchor = 0;
+        for (int k = 0; k <= last; ++k) {
+            BwdSample Sx;
+            bwd_sample<VT, OP, LIT>(P, tab, R, rs, k, false, Sx);
+            float Tn = T * (1.0f - Sx.a);
+            if (!(Tn >= kTinyT)) break;
+            T = Tn;
+            anchor = k + 1;
+        }
+        Ta = T;
+    }
+    float Bk1[3] = {0.f, 0.f, 0.f};
+    float Pk1 = 1.0f, Q = 1.0f;
+    BwdSample Sm, Sn;
+    float cn[8];
+    DtfRun run;
+    DvRun vrun;
+    int k = has ? last : -1;
+    if (has) {
+        bwd_fetch<VT>(P, R, k, Sm, cn);
+        bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm);
+    }
+    const DvSink glob{nullptr, {0, 0, 0}, 0, 0, 0};
+    // Every chunk moves at least the lane that defines thi one sample on,
+    // so 64 (K_max + 1) chunks finish any wave; the cap only turns a broken
+    // invariant into a wrong gradient instead of a wave that never ends.
+    const long long chunk_cap = 64ll * (wave_max(has ? last : -1) + 2);
+    long long n_chunks = 0;
+    for (;;) {
+        const bool active = k >= 0;
+        if (__ballot(active) == 0ull || ++n_chunks > chunk_cap) break;
+        const double thi = wave_max_nonneg(active ? R.t_in + (double)k * P.step : 0.0);
+        int len = Bp.chunk_len, kstop = k + 1;
+        DvSink sk = glob;
+        for (;;) {
+            const double tlo = thi - (double)len * P.step;
+            int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+            kstop = k + 1;
+            if (active) {
+                // first index past tlo (rounding here only groups the work)
+                const double q = floor((tlo - R.t_in) * P.inv_step) + 1.0;
+                kstop = q <= 0.0 ? 0 : (q > (double)k ? k + 1 : (int)q);
+                // the lane(s) that define thi always own their next sample
+                if (R.t_in + (double)k * P.step >= thi) kstop = min(kstop, k);
+                if (kstop <= k) {
+                    Cell c0, c1;
+                    double pv[3];
+                    lattice_point(P, R, kstop, c0, pv);
+                    lattice_point(P, R, k, c1, pv);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        mn[a] = min(c0.c[a], c1.c[a]);
+                        mx[a] = max(c0.c[a], c1.c[a]);
+                    }
+                }
+            }
+            int lo[3], dim[3];
+            long long nvox = 1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int cmin = wave_min(mn[a]), cmax = wave_max(mx[a]);
+                lo[a] = cmin - 1;                   // the taps reach one voxel below
+                dim[a] = cmax - cmin + 4;           // and two above the cells
+                nvox *= dim[a];
+            }
+            if (nvox <= Bp.box_floats) {
+                sk = DvSink{dvb, {lo[0], lo[1], lo[2]}, dim[0], dim[0] * dim[1], (int)nvox};
+                break;
+            }
+            if (len <= 2) break;                    // straight to dV
+            len >>= 1;
+        }
+        // this lane's samples k .. kstop, back to front
+        while (k >= kstop) {
+            if (!LIT && k > 0) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
+            const float om = 1.0f - Sm.a;
+            if (k < anchor) {
+                Q *= om;
+                const float Tk = Q > 0.0f ? Ta / Q : 0.0f;
+                bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, vrun, sk, Sm, rs, Tk, g, Bk1, Pk1);
+            }
+            Bk1[0] = fmaf(Sm.a, Sm.c[0], om * Bk1[0]);
+            Bk1[1] = fmaf(Sm.a, Sm.c[1], om * Bk1[1]);
+            Bk1[2] = fmaf(Sm.a, Sm.c[2], om * Bk1[2]);
+            Pk1 *= om;
+            if (k > 0) {
+                if (LIT) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
+                bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sn);
+                Sm = Sn;
+            }
+            --k;
+        }
+        dv_flush(P, Bp, sk, vrun);              // a cell run does not outlive its chunk
+        if (sk.lds) {
+            wave_lds_sync();
+            dv_box_flush(P, Bp, sk, lane);
+            wave_lds_sync();
+        }
+    }
+    dtf_flush(P, Bp, lds, run);
+    if (Bp.lds_tf) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) {
+            float w = lds[i];
+            if (w != 0.0f) unsafeAtomicAdd(&Bp.dtf[i], w);
+        }
+    }
+}
+
 template <typename VT>
 static void launch_bwd_t(const RenderParams& P, const ViewSet& S, const BackwardParams& Bp, int op,
                          dim3 grid, dim3 block, size_t lds, hipStream_t s) {
-    if (P.shade == RC_SHADE_NONE)
-        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s, P, S,
+    if (P.shade == RC_SHADE_NONE) {
+        if (Bp.box_floats > 0 || Bp.chunk_len > 0)
+            hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s,
+                               P, S, Bp);
+        else
+            hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s, P,
+                               S, Bp);
+    } else if (op == RC_GRAD_CENTRAL) {
+        hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_CENTRAL, true>), grid, block, lds, s, P, S,
                            Bp);
-    else if (op == RC_GRAD_CENTRAL)
-        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_CENTRAL, true>), grid, block, lds, s, P, S, Bp);
-    else if (op == RC_GRAD_SOBEL3D)
-        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_SOBEL3D, true>), grid, block, lds, s, P, S, Bp);
-    else
-        hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_ZUCKER_HUMMEL, true>), grid, block, lds, s, P,
-                           S, Bp);
+    } else if (op == RC_GRAD_SOBEL3D) {
+        hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_SOBEL3D, true>), grid, block, lds, s, P, S,
+                           Bp);
+    } else {
+        hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_ZUCKER_HUMMEL, true>), grid, block, lds, s,
+                           P, S, Bp);
+    }
 }
 
 }  // namespace rc
@@ -458,11 +719,40 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
     BackwardParams Bp;
     Bp.dvol = grad_volume_dev;
     Bp.dtf = grad_tf_dev;
-    Bp.lds_tf = tf_len <= kBwdLdsEntries;
-    Bp.lds_table = tf_len <= kBwdLdsTable;
     Bp.M4 = tf_len * 4;
     Bp.dbg = P.dbg;
-    size_t lds = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 4 * sizeof(float);
+    // Shaded renders scatter up to 64 voxels per sample, and tables beyond
+    // kBwdLdsEntries cannot be privatised per one-wave block: both go to the
+    // chunked kernel (LDS dV boxes, a table gradient shared by 8 waves).
+    // Unshaded renders with smaller tables keep the per-ray kernel.
+    const bool boxed = sh->model != RC_SHADE_NONE || tf_len > kBwdLdsEntries;
+    size_t lds = 0;
+    int waves = 1;
+    if (boxed) {
+        // LDS a block may take on this device (160 KiB on gfx950)
+        int dev = 0, lds_max = 0;
+        RC_HIP(hipGetDevice(&dev));
+        RC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t budget = (size_t)std::min(lds_max, kBwdLdsBytes);
+        waves = kBwdBoxWaves;
+        Bp.lds_tf = tf_len <= kBwdBoxTfEntries && (size_t)tf_len * 16 + 4096 <= budget;
+        Bp.lds_table = tf_len <= kBwdLdsTable;
+        size_t tf_bytes = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 16;
+        if (tf_bytes + 4096 > budget) {     // no room for the table copy: read it from memory
+            Bp.lds_table = 0;
+            tf_bytes = (Bp.lds_tf ? 1 : 0) * (size_t)tf_len * 16;
+        }
+        Bp.box_floats = (int)std::min<size_t>(kBwdBoxFloats,
+                                              (budget - tf_bytes) / (4 * kBwdBoxWaves));
+        Bp.chunk_len = kBwdChunk;
+        lds = tf_bytes + (size_t)Bp.box_floats * 4 * kBwdBoxWaves;
+    } else {
+        Bp.lds_tf = tf_len <= kBwdLdsEntries;
+        Bp.lds_table = tf_len <= kBwdLdsTable;
+        Bp.box_floats = 0;
+        Bp.chunk_len = 0;
+        lds = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 16;
+    }
     for (int first = 0; first < n_views; first += kMaxViews) {
         ViewSet S;
         S.n = n_views - first < kMaxViews ? n_views - first : kMaxViews;
@@ -476,7 +766,7 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
             off += ((V.W + kBwdTile - 1) / kBwdTile) * ((V.H + kBwdTile - 1) / kBwdTile);
         }
         S.block_off[S.n] = off;
-        dim3 grid((unsigned)off), block(kBwdTile * kBwdTile);
+        dim3 grid((unsigned)((off + waves - 1) / waves)), block(kBwdTile * kBwdTile * waves);
         int op = opt->gradient_op;
         if (v->dtype == RC_U8) launch_bwd_t<uint8_t>(P, S, Bp, op, grid, block, lds, s);
         else if (v->dtype == RC_U16) launch_bwd_t<uint16_t>(P, S, Bp, op, grid, block, lds, s);
