@@ -18,8 +18,8 @@ struct BackwardParams {
     int lds_table;          // 1: read the table from an LDS copy
     int M4;                 // table entries * 4 (the dTF length)
     unsigned int* dbg;      // bounds-checked build: violation counter; else null
-    int box_floats;         // LDS dV box of the chunked kernel (voxels); 0 = per-ray kernel
-    int chunk_len;          // first chunk length of the chunked kernel, lattice steps
+    int box_bytes;          // LDS per wave of the chunked kernel (dV box + voxel box)
+    int chunk_len;          // first chunk length of the chunked kernel, lattice steps; 0 = per-ray kernel
 };
 
 constexpr int kBwdTile = 8;               // 8x8 pixels, one wave per workgroup
@@ -29,11 +29,12 @@ constexpr float kTinyT = 1e-30f;
 // The chunked kernel: blocks of kBwdBoxWaves waves (one tile each) share
 // the table gradient in LDS -- tables up to kBwdBoxTfEntries entries, so a
 // whole block's samples, which mostly read a few hot entries, meet in LDS
-// instead of at a few device addresses -- and each wave has a dV box of up
-// to kBwdBoxFloats voxels in what the 160 KiB of LDS leave.
+// instead of at a few device addresses -- and each wave has up to
+// kBwdBoxBytes of what the 160 KiB of LDS leave for its chunk's dV box and
+// staged voxel box.
 constexpr int kBwdBoxWaves = 8;
 constexpr int kBwdBoxTfEntries = 4096;
-constexpr int kBwdBoxFloats = 4096;
+constexpr int kBwdBoxBytes = 20480;
 constexpr int kBwdLdsBytes = 160 * 1024;
 constexpr int kBwdChunk = 16;             // first chunk length in lattice steps
 
@@ -103,21 +104,31 @@ struct BwdSample {
 // Sample k's position, footprint offsets and its cell's 8 voxels (the loads
 // are issued here and consumed by bwd_finish, so a caller can overlap them
 // with other work).
-template <typename VT>
-__device__ __forceinline__ void bwd_fetch(const RenderParams& P, const Ray& R, int k,
-                                          BwdSample& S, float corner[8]) {
+// The source is the bricked volume (GlobalSrc) or a chunk's voxel box
+// staged in LDS (LdsSrc, which holds the same values).
+template <typename VT, typename Src>
+__device__ __forceinline__ void bwd_fetch_from(const RenderParams& P, const Ray& R, int k,
+                                               const Src& src, BwdSample& S, float corner[8]) {
     lattice_point(P, R, k, S.C, S.pv);
-    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
-                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
     src.offsets(S.C, S.ox, S.oy, S.oz);
     load_corners<VT>(src.base, S.ox, S.oy, S.oz, corner);
 }
 
+template <typename VT>
+__device__ __forceinline__ void bwd_fetch(const RenderParams& P, const Ray& R, int k,
+                                          BwdSample& S, float corner[8]) {
+    const GlobalSrc<VT> src{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
+                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
+    bwd_fetch_from<VT>(P, R, k, src, S, corner);
+}
+
+// base: the voxel source the sample was fetched from (its offsets S.ox ..),
+// null for the bricked volume.
 template <typename VT, int OP, bool LIT>
 __device__ __forceinline__ void bwd_finish(const RenderParams& P, const float4* tab,
                                            const RayShade& rs, bool lit, const float corner[8],
-                                           BwdSample& S) {
-    const VT* base = (const VT*)P.vox;
+                                           BwdSample& S, const VT* base = nullptr) {
+    if (!base) base = (const VT*)P.vox;
     float v = trilinear(corner, S.C);
     S.vn = (v - P.vmin) * P.inv_range;
     float uu = fminf(fmaxf(S.vn, 0.0f), 1.0f) * P.Mm1;
@@ -523,7 +534,7 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
     // LDS: the block's table gradient (shared by its waves), the table copy,
     // then one dV box per wave
     const int tf_floats = (Bp.lds_tf ? P.M * 4 : 0) + (Bp.lds_table ? P.M * 4 : 0);
-    float* dvb = lds + tf_floats + wave * Bp.box_floats;
+    float* dvb = lds + tf_floats + wave * (Bp.box_bytes / 4);
     if (Bp.lds_tf)
         for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) lds[i] = 0.0f;
     if (Bp.lds_table) {
@@ -531,7 +542,7 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
         for (int i = threadIdx.x; i < P.M; i += blockDim.x) t[i] = P.tf[i];
         tab = t;
     }
-    for (int i = lane; i < Bp.box_floats; i += 64) dvb[i] = 0.0f;
+    for (int i = lane; i < Bp.box_bytes / 4; i += 64) dvb[i] = 0.0f;
     __syncthreads();
     // one tile per wave, in the work order of raycast_bwd
     int b = 0, v = view_of_unit(S, 1, (int)blockIdx.x * kBwdBoxWaves + wave, b);
@@ -576,16 +587,19 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
     }
     float Bk1[3] = {0.f, 0.f, 0.f};
     float Pk1 = 1.0f, Q = 1.0f;
-    BwdSample Sm, Sn;
-    float cn[8];
     DtfRun run;
     DvRun vrun;
     int k = has ? last : -1;
-    if (has) {
-        bwd_fetch<VT>(P, R, k, Sm, cn);
-        bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm);
-    }
+    const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
+                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
     const DvSink glob{nullptr, {0, 0, 0}, 0, 0, 0};
+    // This wave's LDS: the dV box grows from the start, the chunk's voxel box
+    // sits at the end.  [0, zero_end) is known to be all zero; the dV box
+    // must start zeroed, so where it grows into bytes a voxel box used it is
+    // cleared first.
+    unsigned char* wl = (unsigned char*)dvb;
+    const int wave_bytes = Bp.box_bytes;
+    int zero_end = wave_bytes;
     // Every chunk moves at least the lane that defines thi one sample on,
     // so 64 (K_max + 1) chunks finish any wave; the cap only turns a broken
     // invariant into a wrong gradient instead of a wave that never ends.
@@ -597,6 +611,7 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
         const double thi = wave_max_nonneg(active ? R.t_in + (double)k * P.step : 0.0);
         int len = Bp.chunk_len, kstop = k + 1;
         DvSink sk = glob;
+        int vlo[3] = {0, 0, 0}, vdim[3] = {0, 0, 0}, vbytes = 0;
         for (;;) {
             const double tlo = thi - (double)len * P.step;
             int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
@@ -620,24 +635,64 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
                 }
             }
             int lo[3], dim[3];
-            long long nvox = 1;
+            long long nvox = 1, vvox = 1;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const int cmin = wave_min(mn[a]), cmax = wave_max(mx[a]);
                 lo[a] = cmin - 1;                   // the taps reach one voxel below
                 dim[a] = cmax - cmin + 4;           // and two above the cells
                 nvox *= dim[a];
+                // the voxel box: the same span, widened to even bounds for
+                // the 2x2x2 group loads of stage_box
+                vlo[a] = lo[a] & ~1;
+                vdim[a] = ((cmax + 2) | 1) - vlo[a] + 1;
+                vvox *= vdim[a];
             }
-            if (nvox <= Bp.box_floats) {
+            const long long dvb16 = (nvox * 4 + 15) & ~15ll;
+            // unshaded samples read 8 voxels each: staging does not pay
+            // (measured); shaded ones read the operator's 64
+            const long long vb16 = LIT ? (vvox * (long long)sizeof(VT) + 15) & ~15ll : 0;
+            if (dvb16 + vb16 <= wave_bytes) {
                 sk = DvSink{dvb, {lo[0], lo[1], lo[2]}, dim[0], dim[0] * dim[1], (int)nvox};
+                vbytes = (int)vb16;
                 break;
             }
-            if (len <= 2) break;                    // straight to dV
+            if (len <= 2) break;                    // read and scatter in device memory
             len >>= 1;
         }
-        // this lane's samples k .. kstop, back to front
+        const VT* vbox = nullptr;
+        if (sk.lds && !LIT) {
+            if (zero_end < sk.n * 4) {
+                for (int i = zero_end / 4 + lane; i < sk.n; i += 64) dvb[i] = 0.0f;
+                zero_end = sk.n * 4;
+            }
+            wave_lds_sync();
+        } else if (sk.lds) {
+            if (zero_end < sk.n * 4) {
+                for (int i = zero_end / 4 + lane; i < sk.n; i += 64) dvb[i] = 0.0f;
+                zero_end = sk.n * 4;
+            }
+            VT* vb = (VT*)(wl + wave_bytes - vbytes);
+            stage_box<VT, VT>(P, vb, vlo, vdim, lane);
+            zero_end = min(zero_end, wave_bytes - vbytes);
+            wave_lds_sync();
+            vbox = vb;
+        }
+        const LdsSrc<VT> lsrc{vbox, {vlo[0], vlo[1], vlo[2]}, vdim[0], vdim[0] * vdim[1],
+                              vdim[0] * vdim[1] * vdim[2], P.dbg};
+        // this lane's samples k .. kstop, back to front, read from the box
+        // (every one of them lies in it: their cells lie between the end
+        // cells the box was built from) or from the bricked volume
         while (k >= kstop) {
-            if (!LIT && k > 0) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
+            BwdSample Sm;
+            float cn[8];
+            if (vbox) {
+                bwd_fetch_from<VT>(P, R, k, lsrc, Sm, cn);
+                bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm, vbox);
+            } else {
+                bwd_fetch_from<VT>(P, R, k, gsrc, Sm, cn);
+                bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm);
+            }
             const float om = 1.0f - Sm.a;
             if (k < anchor) {
                 Q *= om;
@@ -648,11 +703,6 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
             Bk1[1] = fmaf(Sm.a, Sm.c[1], om * Bk1[1]);
             Bk1[2] = fmaf(Sm.a, Sm.c[2], om * Bk1[2]);
             Pk1 *= om;
-            if (k > 0) {
-                if (LIT) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
-                bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sn);
-                Sm = Sn;
-            }
             --k;
         }
         dv_flush(P, Bp, sk, vrun);              // a cell run does not outlive its chunk
@@ -676,7 +726,7 @@ template <typename VT>
 static void launch_bwd_t(const RenderParams& P, const ViewSet& S, const BackwardParams& Bp, int op,
                          dim3 grid, dim3 block, size_t lds, hipStream_t s) {
     if (P.shade == RC_SHADE_NONE) {
-        if (Bp.box_floats > 0 || Bp.chunk_len > 0)
+        if (Bp.chunk_len > 0)
             hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s,
                                P, S, Bp);
         else
@@ -742,14 +792,14 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
             Bp.lds_table = 0;
             tf_bytes = (Bp.lds_tf ? 1 : 0) * (size_t)tf_len * 16;
         }
-        Bp.box_floats = (int)std::min<size_t>(kBwdBoxFloats,
-                                              (budget - tf_bytes) / (4 * kBwdBoxWaves));
+        Bp.box_bytes = (int)(std::min<size_t>(kBwdBoxBytes, (budget - tf_bytes) / kBwdBoxWaves) &
+                             ~(size_t)15);
         Bp.chunk_len = kBwdChunk;
-        lds = tf_bytes + (size_t)Bp.box_floats * 4 * kBwdBoxWaves;
+        lds = tf_bytes + (size_t)Bp.box_bytes * kBwdBoxWaves;
     } else {
         Bp.lds_tf = tf_len <= kBwdLdsEntries;
         Bp.lds_table = tf_len <= kBwdLdsTable;
-        Bp.box_floats = 0;
+        Bp.box_bytes = 0;
         Bp.chunk_len = 0;
         lds = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 16;
     }
