@@ -234,10 +234,12 @@ __device__ __forceinline__ void cell_of(const RenderParams& P, const double p3[3
         // nearest sampling (Section 3.3, round half up): the cell of the
         // rounded point with fraction 0, so the trilinear and stencil code
         // reduce exactly to that voxel
-        double fl = floor(P.nearest ? p + 0.5 : p);
-        fl = fmin(fmax(fl, -2.0), 1.0e7);
+        // (round_bias is 0.5 for nearest sampling, else 0; frac_keep 0 or 1).
+        // Sample points lie in the sampling box, [0, n - 1] in voxel units
+        // up to rounding, so the cell index fits an int without a clamp.
+        const double fl = floor(p + P.round_bias);
         C.c[a] = (int)fl;
-        C.fr[a] = P.nearest ? 0.0f : (float)(p - fl);
+        C.fr[a] = (float)(p - fl) * P.frac_keep;
     }
 }
 
@@ -326,7 +328,36 @@ struct LdsSrc {
         }
 #endif
     }
+    // The same footprint as a per-lane base (the footprint's first voxel)
+    // plus offsets that are the same for every lane: x steps 0..3 and the
+    // chunk's row and slab strides.  A footprint voxel's address is then one
+    // add of a wave-uniform row offset, with the x step in the instruction's
+    // immediate offset.
+    __device__ __forceinline__ const VT* lane_offsets(const Cell& C, int ox[4], int oy[4],
+                                                      int oz[4]) const {
+        offsets(C, ox, oy, oz);
+        const int first = ox[0] + oy[0] + oz[0];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ox[i] = i;
+            oy[i] = i * bx;
+            oz[i] = i * bxy;
+        }
+        return base + first;
+    }
 };
+
+template <typename VT>
+__device__ __forceinline__ const VT* footprint(const GlobalSrc<VT>& s, const Cell& C, int ox[4],
+                                               int oy[4], int oz[4]) {
+    s.offsets(C, ox, oy, oz);
+    return s.base;
+}
+template <typename VT>
+__device__ __forceinline__ const VT* footprint(const LdsSrc<VT>& s, const Cell& C, int ox[4],
+                                               int oy[4], int oz[4]) {
+    return s.lane_offsets(C, ox, oy, oz);
+}
 
 // ---------------------------------------------------------------- sampling
 // Trilinear interpolation as 7 lerps, x then y then z (Section 3.4, eq. 2).
@@ -727,10 +758,10 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
                                              const double pv[3], const RayShade& rs,
                                              LaneState& S) {
     int ox[4], oy[4], oz[4];
-    src.offsets(C, ox, oy, oz);
-    float corner[8];
     using ET = typename Src::elem;          // element type of the source
-    float v = sample_value<ET>(src.base, ox, oy, oz, C, corner);
+    const ET* base = footprint(src, C, ox, oy, oz);
+    float corner[8];
+    float v = sample_value<ET>(base, ox, oy, oz, C, corner);
     float4 rgba = tf_lookup(P, v);
     float a = rgba.w;
     if (a == 0.0f) return false;
@@ -739,7 +770,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     float c[3] = {rgba.x, rgba.y, rgba.z};
     if (LIT) {
         float g[3];
-        gradient<ET, OP, true>(P, src.base, ox, oy, oz, C, g, corner);
+        gradient<ET, OP, true>(P, base, ox, oy, oz, C, g, corner);
         shade(P, rgba, g, pv, rs, c);
     }
     float ta = S.T * a;

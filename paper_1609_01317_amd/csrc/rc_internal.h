@@ -102,6 +102,8 @@ struct RenderParams {
     float tau;
     int skip;
     int nearest;                // 1: nearest-voxel sampling
+    double round_bias;          // 0.5 with nearest sampling (round half up), else 0
+    float frac_keep;            // 0 with nearest sampling (cell fraction 0), else 1
     float ocorr;                // opacity-correction exponent step / ref_step, 0 = off
     // adaptive sampling: samples in bricks whose range is <= adapt_range
     // advance by adapt steps; their opacity exponent is adapt_e (else ocorr)

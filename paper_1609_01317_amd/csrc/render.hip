@@ -420,6 +420,8 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
     P.tau = opt->ert_threshold;
     P.skip = opt->skip_empty;
     P.nearest = opt->sampling == RC_SAMPLE_NEAREST;
+    P.round_bias = P.nearest ? 0.5 : 0.0;
+    P.frac_keep = P.nearest ? 0.0f : 1.0f;
     // exponent 1 is the identity: left off (0) so no kernel meets 0^0
     double e = opt->opacity_ref_step > 0.0f ? opt->step / (double)opt->opacity_ref_step : 0.0;
     P.ocorr = e == 1.0 ? 0.0f : (float)e;
