@@ -68,7 +68,8 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1609_01317_amd", "csrc")
     files = [os.path.join(csrc, f) for f in ("batch.hip", "march.h", "rc_internal.h",
-                                               "render.hip")]
+                                               "render.hip", "persist.h", "persist.hip",
+                                               "adaptive.h")]
     files.append(os.path.join(ROOT, "include", "rc.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -93,6 +94,19 @@ def recorded_traffic(views_per_launch):
         return None
     m = re.search(r"hbm_bytes_per_launch\s+raycast_batch:\s*([0-9.eE+]+)", text)
     return float(m.group(1)) if m else None
+
+
+def recorded_l2(views_per_launch):
+    """L2 figures of one raycast_batch launch from the committed counter
+    summary (TCC_READ_SECTORS x 32 B read through L2, TCC_HIT / (TCC_HIT +
+    TCC_MISS)), or (None, None) under the same conditions as
+    recorded_traffic."""
+    if recorded_traffic(views_per_launch) is None:
+        return None, None
+    text = open(PROFILE).read()
+    b = re.search(r"l2_read_bytes_per_launch\s+raycast_batch:\s*([0-9.eE+]+)", text)
+    h = re.search(r"l2_hit_rate\s+raycast_batch:\s*([0-9.eE+]+)", text)
+    return (float(b.group(1)) if b else None), (float(h.group(1)) if h else None)
 
 
 def log(*a):
@@ -238,10 +252,18 @@ def roofline(render_ms, counts, views_per_launch):
     avg_ms = float(np.mean(render_ms))
     flops = flops_total / launches
     achieved = flops / (avg_ms * 1e-3) / 1e12
+    traffic = recorded_traffic(views_per_launch)
+    l2_bytes, l2_hit = recorded_l2(views_per_launch)
     return {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-        "traffic": recorded_traffic(views_per_launch),
+        "traffic": traffic,
+        # achieved HBM and L2 rates of the same launch: counter bytes per
+        # launch over the launch time measured here
+        "hbm_gbs": round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic else None,
+        "hbm_frac": round(traffic / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if traffic else None,
+        "l2_gbs": round(l2_bytes / (avg_ms * 1e-3) / 1e9, 1) if l2_bytes else None,
+        "l2_hit": l2_hit,
         "kernel": "raycast_batch (one launch = the 108 views of the three operators' orbits)",
         "avg_launch_ms": round(avg_ms, 4),
         "algorithmic_flops_per_launch": flops,
