@@ -154,9 +154,9 @@ typedef struct {
  *   out       receives the handle (NULL on failure)
  * Errors: RC_E_INVALID, RC_E_OOM, RC_E_DEVICE.
  */
-rc_status rc_create_volume(const void* src_dev, int nx, int ny, int nz, rc_dtype dtype,
-                           const double spacing[3], float vmin, float vmax, void* stream,
-                           rc_volume** out);
+rc_status rc_create_volume(const void* src_dev, int nx, int ny, int nz,
+                           int32_t dtype /* rc_dtype */, const double spacing[3], float vmin,
+                           float vmax, void* stream, rc_volume** out);
 
 /* Overwrite the voxels of `vol` from a grid of the same shape and dtype.
  * If rc_build_bricks ran before, the brick ranges are rebuilt on the same

@@ -140,17 +140,19 @@ using namespace rc;
 
 extern "C" const char* rc_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" rc_status rc_create_volume(const void* src_dev, int nx, int ny, int nz, rc_dtype dtype,
-                                      const double spacing[3], float vmin, float vmax,
-                                      void* stream, rc_volume** out) {
+extern "C" rc_status rc_create_volume(const void* src_dev, int nx, int ny, int nz,
+                                      int32_t dtype_in, const double spacing[3], float vmin,
+                                      float vmax, void* stream, rc_volume** out) {
     if (!out) return fail(RC_E_INVALID, "rc_create_volume: out is NULL");
     *out = nullptr;
     if (!src_dev) return fail(RC_E_INVALID, "rc_create_volume: src_dev is NULL");
     if (!spacing) return fail(RC_E_INVALID, "rc_create_volume: spacing is NULL");
     if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
         return fail(RC_E_INVALID, "rc_create_volume: dims %d x %d x %d outside 1..4096", nx, ny, nz);
-    if (dtype != RC_U8 && dtype != RC_U16 && dtype != RC_F32)
-        return fail(RC_E_INVALID, "rc_create_volume: unknown dtype %d", (int)dtype);
+    // an int on the ABI: an out-of-range value must not be held in the enum
+    if (dtype_in != RC_U8 && dtype_in != RC_U16 && dtype_in != RC_F32)
+        return fail(RC_E_INVALID, "rc_create_volume: unknown dtype %d", (int)dtype_in);
+    const rc_dtype dtype = (rc_dtype)dtype_in;
     for (int a = 0; a < 3; ++a)
         if (!(std::isfinite(spacing[a]) && spacing[a] > 0.0))
             return fail(RC_E_INVALID, "rc_create_volume: spacing[%d] must be finite and > 0", a);
