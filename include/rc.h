@@ -281,6 +281,9 @@ rc_status rc_batch_create(const rc_batch_item* items, int n, const rc_batch_conf
  * NULL); use_graph = 0 launches eagerly.  Errors: RC_E_INVALID, RC_E_DEVICE. */
 rc_status rc_batch_render(rc_batch* b, int use_graph, void* stream);
 
+/* Release a batch (its descriptors, queue, masks and captured graph) after
+ * its device has finished all its work, as rc_destroy_volume.  NULL is
+ * ignored. */
 void rc_batch_destroy(rc_batch* b);
 
 /* create + render (eager) + destroy: one call for one-off batches. */
@@ -393,8 +396,11 @@ rc_status rc_render_surface(const rc_volume* vol, const rc_camera* cam, const fl
                             int tf_len, const rc_shading* sh, const rc_surface_options* opt,
                             float* out_rgba_dev, float* t_hit_dev, void* stream);
 
-/* Release a handle and its device memory (synchronises with the device).
- * NULL is ignored. */
+/* Release a handle and its device memory.  Waits until the volume's device
+ * has finished all its work first (renders may have read the volume on any
+ * stream; the wait is on the volume's device whichever device is current),
+ * so destroy handles where stalling that device's other streams is
+ * acceptable.  NULL is ignored. */
 void rc_destroy_volume(rc_volume* vol);
 
 /* Message for the last non-OK status returned on the calling thread. */

@@ -394,14 +394,20 @@ extern "C" rc_status rc_batch_render(rc_batch* b, int use_graph, void* stream) {
     return RC_OK;
 }
 
+// As rc_destroy_volume: the batch may have been rendered on several
+// streams, so its memory is released once its device is idle.
 extern "C" void rc_batch_destroy(rc_batch* b) {
     if (!b) return;
+    int cur = -1;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != b->device;
+    if (other) (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();
     if (b->captured) {
         (void)hipGraphExecDestroy(b->exec);
         (void)hipGraphDestroy(b->graph);
     }
     (void)hipFree(b->dmem);
+    if (other) (void)hipSetDevice(cur);
     delete b;
 }
 

@@ -204,10 +204,18 @@ extern "C" rc_status rc_build_bricks(rc_volume* v, int brick_edge, void* stream)
     return launch_minmax(v, (hipStream_t)stream);
 }
 
+// The handle is not tied to one stream (renders may read it on several),
+// so its memory is released after the volume's device has finished all
+// work (hipFree waits for that device as well); the wait is on the
+// volume's own device, made current for the call.
 extern "C" void rc_destroy_volume(rc_volume* v) {
     if (!v) return;
+    int cur = -1;
+    const bool other = hipGetDevice(&cur) == hipSuccess && cur != v->device;
+    if (other) (void)hipSetDevice(v->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(v->bricked);
     if (v->brick_range) (void)hipFree(v->brick_range);
+    if (other) (void)hipSetDevice(cur);
     delete v;
 }
