@@ -2,21 +2,25 @@
 // rate).  A sample in an 8^3 brick whose value range is at most adapt_range
 // advances its ray by adapt steps, any other by one; each sample's opacity
 // is corrected to the distance it stands for.  The sample positions depend
-// on the bricks met along each ray, so there is no shared lattice for the
-// wave to chunk: each lane marches its own ray and gathers straight from the
-// bricked volume.  Arithmetic per sample is the volume mode's (march.h).
-// The per-tile march (adaptive_tile, adaptive.h) is shared with the
-// persistent batched kernel.
+// on the bricks met along each ray, so there is no lattice shared by the
+// rays; shaded renders still march a tile's rays together in chunks of ray
+// parameter with LDS-staged boxes (adaptive.h).  Arithmetic per sample is
+// the volume mode's (march.h).  The per-tile march (adaptive_tile) is
+// shared with the persistent batched kernel.
 #include "adaptive.h"
 
 namespace rc {
 
+// One wave per tile, three waves per SIMD and a 12 KiB box, as the
+// fixed-step shaded kernel.
 template <typename VT, int OP>
-__global__ __launch_bounds__(64) void raycast_adaptive(RenderParams P) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void raycast_adaptive(
+    RenderParams P) {
+    __shared__ __align__(16) unsigned char lds[kWaveLdsBytes];
     const ViewParams& V = P.view;
     int tile = tile_of_block(blockIdx.x, V.tiles_x, V.n_tiles / V.tiles_x);
     if (tile < 0) return;
-    adaptive_tile<VT, OP>(P, V, tile, threadIdx.x);
+    adaptive_tile<VT, OP>(P, V, tile, threadIdx.x, lds, kWaveLdsBytes);
 }
 
 template <typename VT>

@@ -148,7 +148,7 @@ __device__ __forceinline__ void bwd_finish(const RenderParams& P, const float4* 
         S.da_dtf = (om > 0.0f || P.ocorr >= 1.0f)
                        ? P.ocorr * __builtin_amdgcn_exp2f((P.ocorr - 1.0f) * __builtin_amdgcn_logf(om))
                        : 0.0f;
-        if (S.a != 0.0f) S.a = correct_opacity(P, S.a);
+        if (S.a != 0.0f) S.a = correct_opacity(P.ocorr, S.a);
     }
     S.c[0] = S.rgba.x; S.c[1] = S.rgba.y; S.c[2] = S.rgba.z;
     if (LIT && lit) {

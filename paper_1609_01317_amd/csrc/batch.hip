@@ -30,6 +30,7 @@ struct MaskJob {
     int nbx, nby, nbz, nsx, nsy;
     long long nsuper;
     long long super_off;        // offset into the concatenated super mask array
+    float adapt_range;          // detail-poor bound of adaptive items, NaN otherwise
 };
 
 // ---------------------------------------------------------------- kernels
@@ -88,8 +89,8 @@ __global__ __launch_bounds__(256) void batch_mask(const MaskJob* __restrict__ jo
     mask_all[g] = (prefix[ihi + 1] - prefix[ilo]) == 0;
 }
 
-// one thread per super-brick of every mask job (same rule as the single-render
-// super mask: empty iff all of its bricks are)
+// one thread per super-brick of every mask job (same flags as the
+// single-render super mask)
 __global__ __launch_bounds__(256) void batch_super(const MaskJob* __restrict__ jobs, int njobs,
                                                    long long total,
                                                    const uint8_t* __restrict__ mask_all,
@@ -108,12 +109,19 @@ __global__ __launch_bounds__(256) void batch_super(const MaskJob* __restrict__ j
     int sx = (int)(sidx % J.nsx);
     long long rest = sidx / J.nsx;
     int sy = (int)(rest % J.nsy), sz = (int)(rest / J.nsy);
-    uint8_t all = 1;
+    const bool adaptive = !isnan(J.adapt_range);      // else no brick range is read
+    bool all = true, all_poor = adaptive, no_poor = true;
     for (int bz = sz * 4; bz < min(sz * 4 + 4, J.nbz); ++bz)
         for (int by = sy * 4; by < min(sy * 4 + 4, J.nby); ++by)
-            for (int bx = sx * 4; bx < min(sx * 4 + 4, J.nbx); ++bx)
-                all &= mask[((long long)bz * J.nby + by) * J.nbx + bx];
-    super_all[g] = all;
+            for (int bx = sx * 4; bx < min(sx * 4 + 4, J.nbx); ++bx) {
+                const long long b = ((long long)bz * J.nby + by) * J.nbx + bx;
+                all = all && mask[b] != 0;
+                const bool poor = adaptive && brick_poor(J.range[b], J.adapt_range);
+                all_poor = all_poor && poor;
+                no_poor = no_poor && !poor;
+            }
+    super_all[g] = (all ? kSuperEmpty : 0) | (all_poor ? kSuperPoor : 0) |
+                   (no_poor ? kSuperRich : 0);
 }
 
 }  // namespace rc
@@ -170,7 +178,7 @@ static rc_batch_config default_config() { return rc_batch_config{8, 1, 8, 1, 0, 
 // the volume's type for central differences, nothing for unshaded items
 // (they read the bricked volume directly).
 static int item_box_bytes(const rc_batch_item& it, const rc_batch_config& c) {
-    if (it.sh.model == RC_SHADE_NONE || it.opt.adapt_factor > 1) return 16;
+    if (it.sh.model == RC_SHADE_NONE) return 16;
     if (it.opt.gradient_op == RC_GRAD_CENTRAL)
         return c.box_bytes_cd ? c.box_bytes_cd : kBatchWaveLdsBytes;
     return c.box_bytes_grad ? c.box_bytes_grad : kWaveLdsBytes;
@@ -189,8 +197,10 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     std::vector<RenderParams> P(n);
     std::vector<int> kinds(n), tiles(n);
     std::vector<MaskJob> jobs;
-    std::vector<int> job_of(n, -1);        // items of one volume and table share a mask
-    std::map<std::tuple<const void*, const void*, int>, int> job_index;
+    // items of one volume and table (and, for adaptive items, one detail-poor
+    // bound) share a mask
+    std::vector<int> job_of(n, -1);
+    std::map<std::tuple<const void*, const void*, int, uint32_t>, int> job_index;
     long long total_bricks = 0, total_prefix = 0, total_super = 0;
     for (int i = 0; i < n; ++i) {
         const rc_batch_item& it = items[i];
@@ -207,8 +217,11 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
         kinds[i] = item_kind(it.vol, &it.sh, &it.opt);
         tiles[i] = P[i].view.n_tiles;
         if (it.opt.skip_empty) {
+            const float adapt_range = it.opt.adapt_factor > 1 ? it.opt.adapt_range : NAN;
+            uint32_t adapt_bits;
+            std::memcpy(&adapt_bits, &adapt_range, sizeof(adapt_bits));
             const auto key = std::make_tuple((const void*)it.vol, (const void*)it.tf_rgba_dev,
-                                             it.tf_len);
+                                             it.tf_len, adapt_bits);
             const auto found = job_index.find(key);
             if (found != job_index.end()) {
                 job_of[i] = found->second;
@@ -233,6 +246,7 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
             J.nsy = it.vol->nsy;
             J.nsuper = it.vol->nsuper;
             J.super_off = total_super;
+            J.adapt_range = adapt_range;
             total_bricks += J.nbricks;
             total_prefix += it.tf_len + 1;
             total_super += J.nsuper;

@@ -33,6 +33,12 @@ __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// Adaptive sampling (Section 5.2): a brick is detail-poor when its value
+// range is at most adapt_range (NaN: no brick is).
+__device__ __forceinline__ bool brick_poor(float2 r, float adapt_range) {
+    return (double)r.y - (double)r.x <= (double)adapt_range;
+}
+
 // ---------------------------------------------------------------- wave helpers
 // Wave-wide min / max through DPP lane moves (quad permutes, row mirrors,
 // row broadcasts 15 and 31): the total lands in lane 63 and is read back as
@@ -723,10 +729,10 @@ struct MarchOut {
     unsigned chunks_staged, chunks_empty, chunks_direct;  // per wave (uniform)
 };
 
-// Opacity correction for the sample distance: a = 1 - (1 - a_tf)^(step/ref),
-// through hardware log2 / exp2 (0 stays 0, 1 stays 1).
-__device__ __forceinline__ float correct_opacity(const RenderParams& P, float a) {
-    return 1.0f - __builtin_amdgcn_exp2f(P.ocorr * __builtin_amdgcn_logf(1.0f - a));
+// Opacity correction for the sample distance: a = 1 - (1 - a_tf)^e with
+// e = step / ref, through hardware log2 / exp2 (0 stays 0, 1 stays 1).
+__device__ __forceinline__ float correct_opacity(float e, float a) {
+    return 1.0f - __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(1.0f - a));
 }
 
 // Per-lane compositing state (Section 3.9, eq. 6 evaluated front to back:
@@ -752,11 +758,12 @@ struct Chunk {
 // One evaluated sample: value, table, and for non-zero opacity the
 // gradient, shading and compositing.  Returns true when the ray terminates.
 // LIT: a shading model is on (the unshaded instantiations carry none of the
-// gradient's registers, so they keep more waves resident).
+// gradient's registers, so they keep more waves resident).  e: the opacity
+// correction exponent of the distance the sample stands for (0 = none).
 template <typename VT, int OP, bool LIT, typename Src>
 __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& src, const Cell& C,
                                              const double pv[3], const RayShade& rs,
-                                             LaneState& S) {
+                                             LaneState& S, float e) {
     int ox[4], oy[4], oz[4];
     using ET = typename Src::elem;          // element type of the source
     const ET* base = footprint(src, C, ox, oy, oz);
@@ -765,7 +772,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     float4 rgba = tf_lookup(P, v);
     float a = rgba.w;
     if (a == 0.0f) return false;
-    if (P.ocorr > 0.0f) a = correct_opacity(P, a);
+    if (e > 0.0f) a = correct_opacity(e, a);
     ++S.shaded;
     float c[3] = {rgba.x, rgba.y, rgba.z};
     if (LIT) {
@@ -815,8 +822,8 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
         // a staged chunk's samples always read the box.
         const bool in = staged;
         S.direct += in ? 0u : 1u;
-        bool term = in ? shade_sample<VT, OP, LIT>(P, lsrc, C, pv, rs, S)
-                       : shade_sample<VT, OP, LIT>(P, gsrc, C, pv, rs, S);
+        bool term = in ? shade_sample<VT, OP, LIT>(P, lsrc, C, pv, rs, S, P.ocorr)
+                       : shade_sample<VT, OP, LIT>(P, gsrc, C, pv, rs, S, P.ocorr);
         if (term) {
             S.k_term = k;
             S.done = true;
@@ -889,9 +896,9 @@ __device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const R
         bool live = false;
         if (lane < nsr) {
             int r0 = lane % sdim[0], r1 = (lane / sdim[0]) % sdim[1], r2 = lane / (sdim[0] * sdim[1]);
-            live = P.super_empty[RC_IDX(P.dbg,
-                                        ((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0,
-                                        (long long)P.nsx * P.nsy * P.nsz)] == 0;
+            live = (P.super_empty[RC_IDX(P.dbg,
+                                         ((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0,
+                                         (long long)P.nsx * P.nsy * P.nsz)] & kSuperEmpty) == 0;
         }
         return __ballot(live) == 0ull;
     }
@@ -923,8 +930,8 @@ __device__ __forceinline__ int entry_index(const RenderParams& P, const Ray& R) 
     const float kmax = (float)R.K;
 #pragma unroll 1
     for (int it = 0; it < ns[0] + ns[1] + ns[2]; ++it) {
-        if (P.super_empty[RC_IDX(P.dbg, (cell[2] * P.nsy + cell[1]) * P.nsx + cell[0],
-                                 (long long)P.nsx * P.nsy * P.nsz)] == 0)
+        if ((P.super_empty[RC_IDX(P.dbg, (cell[2] * P.nsy + cell[1]) * P.nsx + cell[0],
+                                  (long long)P.nsx * P.nsy * P.nsz)] & kSuperEmpty) == 0)
             break;
         int a = kb[0] <= kb[1] ? (kb[0] <= kb[2] ? 0 : 2) : (kb[1] <= kb[2] ? 1 : 2);
         k_enter = kb[a];

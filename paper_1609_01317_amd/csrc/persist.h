@@ -34,7 +34,8 @@ __device__ __forceinline__ void run_unit(const RenderParams& P, int tile, int la
         render_tile<typename VoxOf<K - 9>::type, RC_GRAD_CENTRAL, false>(P, P.view, tile, lane,
                                                                         lds, lds_bytes);
     } else {
-        adaptive_tile<typename VoxOf<(K - 12) / 3>::type, (K - 12) % 3>(P, P.view, tile, lane);
+        adaptive_tile<typename VoxOf<(K - 12) / 3>::type, (K - 12) % 3>(P, P.view, tile, lane, lds,
+                                                                     lds_bytes);
     }
 }
 

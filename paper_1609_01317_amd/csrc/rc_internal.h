@@ -72,6 +72,10 @@ struct ViewParams {
     const float4* grad;         // reverse pass: dL/d(rgba)
 };
 
+// Flags of a super-brick (4x4x4 bricks): every brick empty; every brick
+// detail-poor; no brick detail-poor (the last two for adaptive sampling).
+constexpr uint8_t kSuperEmpty = 1, kSuperPoor = 2, kSuperRich = 4;
+
 struct RenderParams {
     ViewParams view;            // the image of a single render / batch item
     // sampling box (world) and lattice
@@ -112,7 +116,7 @@ struct RenderParams {
     float adapt_e;
     const float2* range;        // per-brick (min, max) value ranges
     const uint8_t* empty;       // per-brick flag, 1 = every sample has alpha 0
-    const uint8_t* super_empty; // per-super-brick flag (4x4x4 bricks), or null
+    const uint8_t* super_empty; // per-super-brick flags (4x4x4 bricks, kSuper*), or null
     int nsx, nsy, nsz;          // super-bricks per axis
     rc_stats* stats;            // kStatSlots consecutive copies, or null
     unsigned int* dbg;          // bounds-checked build: violation counter; else null
@@ -139,11 +143,14 @@ void fill_render_params(RenderParams& P, const rc_volume* v, const rc_camera* ca
                         const float* tf, int tf_len, const rc_shading* sh, const rc_options* opt);
 // Launch the prefix + empty-mask kernels into `mask` (nbricks bytes) using
 // `prefix` (tf_len + 1 ints) as scratch.
+// adapt_range: the detail-poor bound of an adaptive render, NaN otherwise.
 rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
-                            uint8_t* super_mask, int* prefix, hipStream_t st);
-// super_mask[s] = AND of the brick flags of super-brick s (one thread each).
-__global__ void super_mask_kernel(const uint8_t* __restrict__ mask, uint8_t* __restrict__ smask,
-                                  int nbx, int nby, int nbz, int nsx, int nsy, long long nsuper);
+                            uint8_t* super_mask, int* prefix, float adapt_range, hipStream_t st);
+// Super-brick flags (one thread each), kSuperEmpty | kSuperPoor | kSuperRich
+// over the bricks of super-brick s.
+__global__ void super_mask_kernel(const uint8_t* __restrict__ mask, const float2* __restrict__ range,
+                                  float adapt_range, uint8_t* __restrict__ smask, int nbx, int nby,
+                                  int nbz, int nsx, int nsy, long long nsuper);
 // Bytes of per-render skip scratch: brick mask, super-brick mask, prefix counts.
 size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
                           size_t* super_bytes);

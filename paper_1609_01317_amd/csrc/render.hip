@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void empty_mask(const float2* __restrict__ ran
 }
 
 rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uint8_t* mask,
-                            uint8_t* super_mask, int* prefix, hipStream_t st) {
+                            uint8_t* super_mask, int* prefix, float adapt_range, hipStream_t st) {
     float inv_range = (float)(1.0 / ((double)v->vmax - (double)v->vmin));
     hipLaunchKernelGGL(tf_alpha_prefix, dim3(1), dim3(256), 0, st, (const float4*)tf, tf_len,
                        prefix);
@@ -64,13 +64,16 @@ rc_status launch_empty_mask(const rc_volume* v, const float* tf, int tf_len, uin
                        v->vmin, inv_range, (float)(tf_len - 1), mask, v->nbricks);
     RC_HIP(hipGetLastError());
     grid = (unsigned)((v->nsuper + 255) / 256);
-    hipLaunchKernelGGL(super_mask_kernel, dim3(grid), dim3(256), 0, st, mask, super_mask, v->nbx,
-                       v->nby, v->nbz, v->nsx, v->nsy, v->nsuper);
+    hipLaunchKernelGGL(super_mask_kernel, dim3(grid), dim3(256), 0, st, mask, v->brick_range,
+                       adapt_range, super_mask, v->nbx, v->nby, v->nbz, v->nsx, v->nsy,
+                       v->nsuper);
     RC_HIP(hipGetLastError());
     return RC_OK;
 }
 
 __global__ __launch_bounds__(256) void super_mask_kernel(const uint8_t* __restrict__ mask,
+                                                         const float2* __restrict__ range,
+                                                         float adapt_range,
                                                          uint8_t* __restrict__ smask, int nbx,
                                                          int nby, int nbz, int nsx, int nsy,
                                                          long long nsuper) {
@@ -79,12 +82,20 @@ __global__ __launch_bounds__(256) void super_mask_kernel(const uint8_t* __restri
     int sx = (int)(sidx % nsx);
     long long rest = sidx / nsx;
     int sy = (int)(rest % nsy), sz = (int)(rest / nsy);
-    uint8_t all = 1;
+    // a render without adaptive sampling (NaN) reads no brick ranges
+    const bool adaptive = !isnan(adapt_range);
+    bool all = true, all_poor = adaptive, no_poor = true;
     for (int bz = sz * 4; bz < min(sz * 4 + 4, nbz); ++bz)
         for (int by = sy * 4; by < min(sy * 4 + 4, nby); ++by)
-            for (int bx = sx * 4; bx < min(sx * 4 + 4, nbx); ++bx)
-                all &= mask[((long long)bz * nby + by) * nbx + bx];
-    smask[sidx] = all;
+            for (int bx = sx * 4; bx < min(sx * 4 + 4, nbx); ++bx) {
+                const long long b = ((long long)bz * nby + by) * nbx + bx;
+                all = all && mask[b] != 0;
+                const bool poor = adaptive && brick_poor(range[b], adapt_range);
+                all_poor = all_poor && poor;
+                no_poor = no_poor && !poor;
+            }
+    smask[sidx] = (all ? kSuperEmpty : 0) | (all_poor ? kSuperPoor : 0) |
+                  (no_poor ? kSuperRich : 0);
 }
 
 size_t skip_scratch_bytes(const rc_volume* v, int tf_len, size_t* mask_bytes,
@@ -479,7 +490,8 @@ extern "C" rc_status rc_render(const rc_volume* v, const rc_camera* cam, const f
         uint8_t* mask = (uint8_t*)(sp + stat_bytes);
         uint8_t* smask = mask + mask_bytes;
         int* prefix = (int*)(smask + super_bytes);
-        st = launch_empty_mask(v, tf_rgba_dev, tf_len, mask, smask, prefix, s);
+        st = launch_empty_mask(v, tf_rgba_dev, tf_len, mask, smask, prefix,
+                               P.adapt ? P.adapt_range : NAN, s);
         P.empty = mask;
         P.super_empty = smask;
     }
@@ -546,8 +558,8 @@ rc_status render_views_into(const rc_volume* v, const rc_camera* cams, int n_vie
     fill_render_params(P, v, &cams[0], tf_rgba_dev, tf_len, sh, opt);
     const bool lit = sh->model != RC_SHADE_NONE;
     const int kind = item_kind(v, sh, opt);
-    // unshaded and adaptive marches stage nothing
-    const int lds_bytes = opt->adapt_factor > 1 || !lit ? 16
+    // unshaded marches stage nothing
+    const int lds_bytes = !lit ? 16
                           : opt->gradient_op != RC_GRAD_CENTRAL ? kWaveLdsBytes
                                                                 : kBatchWaveLdsBytes;
     P.box_bytes = lds_bytes;
@@ -567,7 +579,8 @@ rc_status render_views_into(const rc_volume* v, const rc_camera* cams, int n_vie
         P.empty = (uint8_t*)sk;
         P.super_empty = P.empty + mask_bytes;
         st = launch_empty_mask(v, tf_rgba_dev, tf_len, (uint8_t*)P.empty,
-                               (uint8_t*)P.super_empty, (int*)(sk + mask_bytes + super_bytes), s);
+                               (uint8_t*)P.super_empty, (int*)(sk + mask_bytes + super_bytes),
+                               P.adapt ? P.adapt_range : NAN, s);
     }
     for (int first = 0; st == RC_OK && first < n_views; first += kMaxViews) {
         ViewSet S;

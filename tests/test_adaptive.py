@@ -104,10 +104,19 @@ def test_adaptive_c2_scale_sampled():
     assert g["stats"][0] < fixed["stats"][0]
 
 
-def test_adaptive_views_and_batches_equal_single_renders():
+@pytest.mark.parametrize("cfg", [None,
+                                 # boxes too small for most chunks: halved chunks, direct reads
+                                 dict(tile_w=8, waves_per_wg=1, wg_per_cu=8, order=1,
+                                      box_bytes_grad=2048, box_bytes_cd=2048, chunk_len=4),
+                                 dict(tile_w=4, waves_per_wg=2, wg_per_cu=4, order=0,
+                                      box_bytes_grad=32768, box_bytes_cd=32768, chunk_len=64)],
+                         ids=["default", "small_boxes", "large_boxes"])
+def test_adaptive_views_and_batches_equal_single_renders(cfg):
     """Adaptive items through the persistent kernel: several views of one
     volume (rc_render_views) and a batch mixing adaptive and fixed-step items
-    of three voxel types are bit-identical to one rc_render each."""
+    of three voxel types are bit-identical to one rc_render each, whatever
+    the batch's box budget and first chunk length (staged and direct chunks
+    read the same voxel values)."""
     specs = [dict(seed=81, dtype=np.uint16, op="sobel3d", shading="blinn_phong", m=4, rng=40.0,
                   ert=0.98, skip=True),
              dict(seed=82, dtype=np.uint8, op="central", shading="none", m=3, rng=10.0, ert=0.0,
@@ -136,7 +145,7 @@ def test_adaptive_views_and_batches_equal_single_renders():
                 items.append({"vol": vol, "camera": c, "tf": tf, "shading": sc.shading,
                               "options": use_opt, "out": torch.full_like(o, -1.0)})
                 refs.append(rc.rc_render(vol, c, tf, sc.shading, use_opt).clone())
-    rc.rc_render_batch(items)
+    rc.rc_render_batch(items, cfg)
     torch.cuda.synchronize()
     for it, ref in zip(items, refs):
         assert torch.equal(it["out"], ref)
