@@ -77,7 +77,7 @@ __device__ __forceinline__ double adaptive_super_step(const RenderParams& P, con
         if (lane < nsr) {
             const int r0 = lane % sdim[0], r1 = (lane / sdim[0]) % sdim[1],
                       r2 = lane / (sdim[0] * sdim[1]);
-            f = P.super_empty[RC_IDX(P.dbg,
+            f = to_gmem(P.super_empty)[RC_IDX(P.dbg,
                                      ((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0,
                                      (long long)P.nsx * P.nsy * P.nsz)];
         }
@@ -209,8 +209,8 @@ __device__ inline void march_wave_adaptive(const RenderParams& P, const Ray& R, 
                 const int r0 = lane % ch.bdim[0], r1 = (lane / ch.bdim[0]) % ch.bdim[1],
                           r2 = lane / (ch.bdim[0] * ch.bdim[1]);
                 const int b = ((ch.blo[2] + r2) * P.nby + ch.blo[1] + r1) * P.nbx + ch.blo[0] + r0;
-                pr = brick_poor(P.range[RC_IDX(P.dbg, b, nbricks)], P.adapt_range);
-                lv = !P.skip || P.empty[RC_IDX(P.dbg, b, nbricks)] == 0;
+                pr = brick_poor(gload(P.range + RC_IDX(P.dbg, b, nbricks)), P.adapt_range);
+                lv = !P.skip || to_gmem(P.empty)[RC_IDX(P.dbg, b, nbricks)] == 0;
             }
             live = __ballot(lv);
             poorm = __ballot(pr);
@@ -261,8 +261,8 @@ __device__ inline void march_wave_adaptive(const RenderParams& P, const Ray& R, 
                     empty = ((live >> bit) & 1ull) == 0;
                 } else {
                     const int b = (b2 * P.nby + b1) * P.nbx + b0;
-                    poor = brick_poor(P.range[RC_IDX(P.dbg, b, nbricks)], P.adapt_range);
-                    empty = P.skip && P.empty[RC_IDX(P.dbg, b, nbricks)] != 0;
+                    poor = brick_poor(gload(P.range + RC_IDX(P.dbg, b, nbricks)), P.adapt_range);
+                    empty = P.skip && to_gmem(P.empty)[RC_IDX(P.dbg, b, nbricks)] != 0;
                 }
                 last = j;
                 if (!empty) {
@@ -332,15 +332,16 @@ __device__ inline void adaptive_lanes(const RenderParams& P, const ViewParams& V
                            (clampi(C.c[1], 0, P.ny - 1) >> 3)) * P.nbx +
                           (clampi(C.c[0], 0, P.nx - 1) >> 3);
             const bool poor =
-                brick_poor(P.range[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)], P.adapt_range);
+                brick_poor(gload(P.range + RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)),
+                           P.adapt_range);
             const double step = poor ? big_step : P.step;
             last = j;
-            if (!(P.skip && P.empty[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)])) {
+            if (!(P.skip && to_gmem(P.empty)[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)])) {
                 ++evaluated;
                 int ox[4], oy[4], oz[4];
                 src.offsets(C, ox, oy, oz);
                 float corner[8];
-                float v = sample_value<VT>(src.base, ox, oy, oz, C, corner);
+                float v = sample_value<VT>(src.gbase(), ox, oy, oz, C, corner);
                 float4 rgba = tf_lookup(P, v);
                 float a = rgba.w;
                 if (a != 0.0f) {
@@ -350,7 +351,7 @@ __device__ inline void adaptive_lanes(const RenderParams& P, const ViewParams& V
                     float c[3] = {rgba.x, rgba.y, rgba.z};
                     if (P.shade != RC_SHADE_NONE) {
                         float g[3];
-                        gradient<VT, OP, true>(P, src.base, ox, oy, oz, C, g, corner);
+                        gradient<VT, OP, true>(P, src.gbase(), ox, oy, oz, C, g, corner);
                         shade(P, rgba, g, pv, rs, c);
                     }
                     float ta = T * a;

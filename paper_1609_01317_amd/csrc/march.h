@@ -33,6 +33,23 @@ __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// Device memory read through global (not flat) loads: a wait for them does
+// not also wait for the wave's LDS traffic, nor a wait for LDS for them.
+template <typename T>
+using gmem = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gmem<T> to_gmem(const T* p) {
+    return (gmem<T>)p;
+}
+// The same for the HIP vector structs (their constructors take generic
+// references): loaded as a builtin vector of 32-bit words.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+    typedef unsigned words __attribute__((ext_vector_type(sizeof(T) / 4)));
+    return __builtin_bit_cast(T, *(gmem<words>)p);
+}
+
 // Adaptive sampling (Section 5.2): a brick is detail-poor when its value
 // range is at most adapt_range (NaN: no brick is).
 __device__ __forceinline__ bool brick_poor(float2 r, float adapt_range) {
@@ -281,6 +298,7 @@ struct GlobalSrc {
     int nx, ny, nz, sy, sz;
     long long n;            // elements of the bricked volume
     unsigned int* dbg;
+    __device__ __forceinline__ gmem<VT> gbase() const { return to_gmem(base); }
     __device__ __forceinline__ void offsets(const Cell& C, int ox[4], int oy[4], int oz[4]) const {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -354,10 +372,10 @@ struct LdsSrc {
 };
 
 template <typename VT>
-__device__ __forceinline__ const VT* footprint(const GlobalSrc<VT>& s, const Cell& C, int ox[4],
-                                               int oy[4], int oz[4]) {
+__device__ __forceinline__ gmem<VT> footprint(const GlobalSrc<VT>& s, const Cell& C, int ox[4],
+                                              int oy[4], int oz[4]) {
     s.offsets(C, ox, oy, oz);
-    return s.base;
+    return s.gbase();
 }
 template <typename VT>
 __device__ __forceinline__ const VT* footprint(const LdsSrc<VT>& s, const Cell& C, int ox[4],
@@ -367,8 +385,8 @@ __device__ __forceinline__ const VT* footprint(const LdsSrc<VT>& s, const Cell& 
 
 // ---------------------------------------------------------------- sampling
 // Trilinear interpolation as 7 lerps, x then y then z (Section 3.4, eq. 2).
-template <typename VT>
-__device__ __forceinline__ void load_corners(const VT* base, const int ox[4], const int oy[4],
+template <typename VT, typename Ptr = const VT*>
+__device__ __forceinline__ void load_corners(Ptr base, const int ox[4], const int oy[4],
                                              const int oz[4], float corner[8]) {
     // corner[(z-1)*4 + (y-1)*2 + (x-1)] = voxel (x, y, z) of the 4x4x4 footprint
 #pragma unroll
@@ -389,15 +407,15 @@ __device__ __forceinline__ float trilinear(const float corner[8], const Cell& C)
     return lerpf(i5, i6, C.fr[2]);
 }
 
-template <typename VT>
-__device__ __forceinline__ float sample_value(const VT* base, const int ox[4], const int oy[4],
+template <typename VT, typename Ptr = const VT*>
+__device__ __forceinline__ float sample_value(Ptr base, const int ox[4], const int oy[4],
                                               const int oz[4], const Cell& C, float corner[8]) {
     load_corners<VT>(base, ox, oy, oz, corner);
     return trilinear(corner, C);
 }
 
-template <typename VT>
-__device__ __forceinline__ float sample_value(const VT* base, const int ox[4], const int oy[4],
+template <typename VT, typename Ptr = const VT*>
+__device__ __forceinline__ float sample_value(Ptr base, const int ox[4], const int oy[4],
                                               const int oz[4], const Cell& C) {
     float corner[8];
     return sample_value<VT>(base, ox, oy, oz, C, corner);
@@ -411,7 +429,7 @@ __device__ __forceinline__ float4 tf_lookup(const RenderParams& P, float v) {
     int i = min((int)uu, P.M - 1);
     int i1 = min(i + 1, P.M - 1);
     float t = uu - (float)i;
-    float4 a = P.tf[RC_IDX(P.dbg, i, P.M)], b = P.tf[RC_IDX(P.dbg, i1, P.M)];
+    const float4 a = gload(P.tf + RC_IDX(P.dbg, i, P.M)), b = gload(P.tf + RC_IDX(P.dbg, i1, P.M));
     return make_float4(lerpf(a.x, b.x, t), lerpf(a.y, b.y, t), lerpf(a.z, b.z, t),
                        lerpf(a.w, b.w, t));
 }
@@ -476,8 +494,8 @@ __device__ __forceinline__ void axis_taps(float t, AxisTaps& k) {
     k.A[3] = a1 * w1;
 }
 
-template <typename VT, int OP, bool HAVE_CORNERS = false>
-__device__ __forceinline__ void gradient(const RenderParams& P, const VT* base, const int ox[4],
+template <typename VT, int OP, bool HAVE_CORNERS = false, typename Ptr = const VT*>
+__device__ __forceinline__ void gradient(const RenderParams& P, Ptr base, const int ox[4],
                                          const int oy[4], const int oz[4], const Cell& C,
                                          float g[3], const float* corner = nullptr) {
     constexpr bool SEP = OpTaps<OP>::kSep;
@@ -665,7 +683,7 @@ __device__ inline void stage_box(const RenderParams& P, LT* lds, const int lo[3]
                                  int lane) {
     using G = typename GroupT<VT>::type;
     using PT = typename PairT<VT>::type;
-    const VT* __restrict__ vox = (const VT*)P.vox;
+    const VT* vox = (const VT*)P.vox;
     const int gx = dim[0] >> 1, gy = dim[1] >> 1, gz = dim[2] >> 1;
     const int ncol = gx * gy;
     const int xmax = P.nbx * 8, ymax = P.nby * 8, zmax = P.nbz * 8;
@@ -687,18 +705,18 @@ __device__ inline void stage_box(const RenderParams& P, LT* lds, const int lo[3]
                     RC_IDX(P.dbg, l0 + bxy + bx + 1, bxy * dim[2]) == 0)
                     continue;
 #endif
-                const G* src = (const G*)(vox + oxy + off_z(z0, P.sz));
+                const G grp = gload((const G*)(vox + oxy + off_z(z0, P.sz)));
                 // l0 and the strides are even: pair-aligned stores
                 if constexpr (std::is_same<LT, float>::value) {
                     float f[8];
-                    group_values<VT>(*src, f);
+                    group_values<VT>(grp, f);
                     *(float2*)(lds + l0) = make_float2(f[0], f[1]);
                     *(float2*)(lds + l0 + bx) = make_float2(f[2], f[3]);
                     *(float2*)(lds + l0 + bxy) = make_float2(f[4], f[5]);
                     *(float2*)(lds + l0 + bxy + bx) = make_float2(f[6], f[7]);
                 } else {
                     PT p[4];
-                    group_pairs<VT>(*src, p);
+                    group_pairs<VT>(grp, p);
                     *(PT*)(lds + l0) = p[0];
                     *(PT*)(lds + l0 + bx) = p[1];
                     *(PT*)(lds + l0 + bxy) = p[2];
@@ -711,8 +729,8 @@ __device__ inline void stage_box(const RenderParams& P, LT* lds, const int lo[3]
                     int x = clampi(x0 + dx, 0, P.nx - 1), y = clampi(y0 + dy, 0, P.ny - 1),
                         z = clampi(z0 + dz, 0, P.nz - 1);
                     lds[RC_IDX(P.dbg, l0 + dz * bxy + dy * bx + dx, bxy * dim[2])] =
-                        (LT)vox[RC_IDX(P.dbg, off_x(x) + off_y(y, P.sy) + off_z(z, P.sz),
-                                       (long long)P.nbx * P.nby * P.nbz * 512)];
+                        (LT)to_gmem(vox)[RC_IDX(P.dbg, off_x(x) + off_y(y, P.sy) + off_z(z, P.sz),
+                                                (long long)P.nbx * P.nby * P.nbz * 512)];
                 }
             }
         }
@@ -766,7 +784,7 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
                                              LaneState& S, float e) {
     int ox[4], oy[4], oz[4];
     using ET = typename Src::elem;          // element type of the source
-    const ET* base = footprint(src, C, ox, oy, oz);
+    const auto base = footprint(src, C, ox, oy, oz);
     float corner[8];
     float v = sample_value<ET>(base, ox, oy, oz, C, corner);
     float4 rgba = tf_lookup(P, v);
@@ -788,6 +806,19 @@ __device__ __forceinline__ bool shade_sample(const RenderParams& P, const Src& s
     return P.tau > 0.0f && 1.0f - S.T >= P.tau;
 }
 
+// A sample whose brick is known to be empty (its opacity is exactly 0).
+__device__ __forceinline__ bool in_empty_brick(const RenderParams& P, const Chunk& ch,
+                                               const Cell& C) {
+    int b0 = clampi(C.c[0], 0, P.nx - 1) >> 3, b1 = clampi(C.c[1], 0, P.ny - 1) >> 3,
+        b2 = clampi(C.c[2], 0, P.nz - 1) >> 3;
+    int r0 = b0 - ch.blo[0], r1 = b1 - ch.blo[1], r2 = b2 - ch.blo[2];
+    if (ch.mask_valid && r0 >= 0 && r1 >= 0 && r2 >= 0 && r0 < ch.bdim[0] && r1 < ch.bdim[1] &&
+        r2 < ch.bdim[2])
+        return ((ch.live >> ((r2 * ch.bdim[1] + r1) * ch.bdim[0] + r0)) & 1ull) == 0;
+    return to_gmem(P.empty)[RC_IDX(P.dbg, (b2 * P.nby + b1) * P.nbx + b0,
+                          (long long)P.nbx * P.nby * P.nbz)] != 0;
+}
+
 // Evaluate lattice samples S.k .. kstop of this lane's ray.  Samples in
 // bricks known to be empty are not evaluated (their opacity is exactly 0,
 // so they change nothing).  A sample reads the LDS box when `staged` and its
@@ -802,19 +833,7 @@ __device__ __forceinline__ void run_samples(const RenderParams& P, const Ray& R,
         Cell C;
         double pv[3];
         lattice_point(P, R, k, C, pv);
-        if (ch.mixed) {
-            int b0 = clampi(C.c[0], 0, P.nx - 1) >> 3, b1 = clampi(C.c[1], 0, P.ny - 1) >> 3,
-                b2 = clampi(C.c[2], 0, P.nz - 1) >> 3;
-            int r0 = b0 - ch.blo[0], r1 = b1 - ch.blo[1], r2 = b2 - ch.blo[2];
-            bool empty;
-            if (ch.mask_valid && r0 >= 0 && r1 >= 0 && r2 >= 0 && r0 < ch.bdim[0] &&
-                r1 < ch.bdim[1] && r2 < ch.bdim[2])
-                empty = ((ch.live >> ((r2 * ch.bdim[1] + r1) * ch.bdim[0] + r0)) & 1ull) == 0;
-            else
-                empty = P.empty[RC_IDX(P.dbg, (b2 * P.nby + b1) * P.nbx + b0,
-                                       (long long)P.nbx * P.nby * P.nbz)] != 0;
-            if (empty) continue;
-        }
+        if (ch.mixed && in_empty_brick(P, ch, C)) continue;
         ++S.evaluated;
         // A lane's cells are monotone along its straight ray (each step of
         // lattice_point is a monotone rounding), so its samples S.k..kstop lie
@@ -896,7 +915,7 @@ __device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const R
         bool live = false;
         if (lane < nsr) {
             int r0 = lane % sdim[0], r1 = (lane / sdim[0]) % sdim[1], r2 = lane / (sdim[0] * sdim[1]);
-            live = (P.super_empty[RC_IDX(P.dbg,
+            live = (to_gmem(P.super_empty)[RC_IDX(P.dbg,
                                          ((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0,
                                          (long long)P.nsx * P.nsy * P.nsz)] & kSuperEmpty) == 0;
         }
@@ -930,7 +949,7 @@ __device__ __forceinline__ int entry_index(const RenderParams& P, const Ray& R) 
     const float kmax = (float)R.K;
 #pragma unroll 1
     for (int it = 0; it < ns[0] + ns[1] + ns[2]; ++it) {
-        if ((P.super_empty[RC_IDX(P.dbg, (cell[2] * P.nsy + cell[1]) * P.nsx + cell[0],
+        if ((to_gmem(P.super_empty)[RC_IDX(P.dbg, (cell[2] * P.nsy + cell[1]) * P.nsx + cell[0],
                                   (long long)P.nsx * P.nsy * P.nsz)] & kSuperEmpty) == 0)
             break;
         int a = kb[0] <= kb[1] ? (kb[0] <= kb[2] ? 0 : 2) : (kb[1] <= kb[2] ? 1 : 2);
@@ -1031,7 +1050,7 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
                 int r0 = lane % ch.bdim[0], r1 = (lane / ch.bdim[0]) % ch.bdim[1],
                     r2 = lane / (ch.bdim[0] * ch.bdim[1]);
                 int b = ((ch.blo[2] + r2) * P.nby + ch.blo[1] + r1) * P.nbx + ch.blo[0] + r0;
-                live = P.empty[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)] == 0;
+                live = to_gmem(P.empty)[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)] == 0;
             }
             ch.live = __ballot(live);
             ch.mixed = ch.live != (nbr == 64 ? ~0ull : ((1ull << nbr) - 1ull));

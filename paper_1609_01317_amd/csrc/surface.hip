@@ -32,7 +32,7 @@ template <typename VT>
 __device__ __forceinline__ float value_of(const GlobalSrc<VT>& src, const Cell& C) {
     int ox[4], oy[4], oz[4];
     src.offsets(C, ox, oy, oz);
-    return sample_value<VT>(src.base, ox, oy, oz, C);
+    return sample_value<VT>(src.gbase(), ox, oy, oz, C);
 }
 
 template <typename VT, int OP>
@@ -86,11 +86,11 @@ __global__ __launch_bounds__(64) void raycast_surface(RenderParams P, SurfacePar
         point_at(P, R, t, C, pv);
         int ox[4], oy[4], oz[4];
         src.offsets(C, ox, oy, oz);
-        float4 rgba = tf_lookup(P, sample_value<VT>(src.base, ox, oy, oz, C));
+        float4 rgba = tf_lookup(P, sample_value<VT>(src.gbase(), ox, oy, oz, C));
         float c[3] = {rgba.x, rgba.y, rgba.z};
         if (P.shade != RC_SHADE_NONE) {
             float g[3];
-            gradient<VT, OP>(P, src.base, ox, oy, oz, C, g);
+            gradient<VT, OP>(P, src.gbase(), ox, oy, oz, C, g);
             RayShade rs;
             ray_shade(P, R, rs);
             shade(P, rgba, g, pv, rs, c);
