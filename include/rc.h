@@ -329,18 +329,18 @@ rc_status rc_render_views(const rc_volume* vol, const rc_camera* cams, int n_vie
  * ---------------------------------------------------------------------- */
 /* rc_render_views without any device allocation (no hipMalloc, hipFree or
  * stream-ordered allocation, none by a library it calls).  The per-call
- * scratch -- the views' item descriptors, the work counter, the brick and
+ * scratch -- the views' item descriptors, the work-queue counters, the brick and
  * super-brick skip masks and the table prefix counts -- lives in one fixed
  * device array of RC_NOALLOC_SCRATCH_BYTES inside the library, one copy per
  * device, held from the first call on that device until the process ends.
- * Its size needed by a call is about 9 KiB + (nbricks + nsuper) bytes +
- * 4 (tf_len + 1) bytes with skip_empty, 9 KiB without (a 512^3 volume with
- * skipping and 4096 entries: about 290 KiB).
+ * Its size needed by a call is about 17 KiB + (nbricks + nsuper) bytes +
+ * 4 (tf_len + 1) bytes with skip_empty, 17 KiB without (a 512^3 volume with
+ * skipping and 4096 entries: about 300 KiB).
  * Arguments, images and errors as rc_render_views (the images are
  * bit-identical to it), plus RC_E_INVALID, before anything is enqueued,
  * when a call needs more scratch than the array holds.  Every call on one
  * device shares that device's array and leaves its contents behind; each
- * call rewrites what it reads (masks, descriptors, and the counter, which a
+ * call rewrites what it reads (masks, descriptors, and the counters, which a
  * kernel clears) before reading it.  Calls that can run at the same time on
  * one device -- on different streams, or enqueued from different threads
  * without ordering -- race on the array: the caller must order them (one

@@ -1,9 +1,9 @@
 // Batched rendering: many images of many volumes in one persistent launch.
 // Each item is the argument set of one rc_render call.  Resident waves pull
-// (item, tile) work units from a device counter until the queue is empty;
-// the per-item empty-brick and super-brick masks are built by three batched
-// kernels; the
-// whole sequence can be captured into a HIP graph and replayed.
+// (item, tile) work units from per-XCD work queues until all are empty
+// (persist.h); the per-item empty-brick and super-brick masks are built by
+// three batched kernels; the whole sequence can be captured into a HIP graph
+// and replayed.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -34,7 +34,10 @@ struct MaskJob {
 };
 
 // ---------------------------------------------------------------- kernels
-__global__ void batch_reset(int* counter) { *counter = 0; }
+// the kQueues work-queue counters of a launch
+__global__ void batch_reset(int* counters) {
+    if (threadIdx.x < kQueues) counters[threadIdx.x * kQueueStride] = 0;
+}
 
 // one workgroup per mask job: prefix counts of non-zero table opacities
 __global__ __launch_bounds__(256) void batch_prefix(const MaskJob* __restrict__ jobs,
@@ -144,7 +147,7 @@ struct rc_batch {
     int* d_kinds;
     int* d_tile_off;
     int* d_order;
-    int* d_counter;
+    int* d_counter;             // kQueues work-queue counters
     MaskJob* d_jobs;
     int* d_prefix;
     uint8_t* d_mask;
@@ -278,7 +281,7 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
     size_t o_toff = align256(o_kinds + sizeof(int) * n);
     size_t o_order = align256(o_toff + sizeof(int) * (n + 1));
     size_t o_counter = align256(o_order + sizeof(int) * n);
-    size_t o_jobs = align256(o_counter + sizeof(int));
+    size_t o_jobs = align256(o_counter + sizeof(int) * kQueues * kQueueStride);
     size_t o_prefix = align256(o_jobs + sizeof(MaskJob) * std::max<size_t>(jobs.size(), 1));
     size_t o_mask = align256(o_prefix + sizeof(int) * std::max<long long>(total_prefix, 1));
     size_t o_super = align256(o_mask + std::max<long long>(total_bricks, 1));
@@ -343,7 +346,7 @@ extern "C" rc_status rc_batch_create(const rc_batch_item* items, int n, const rc
 }
 
 static rc_status enqueue_batch(rc_batch* b, hipStream_t s) {
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, b->d_counter);
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, s, b->d_counter);
     if (b->n_jobs > 0) {
         hipLaunchKernelGGL(batch_prefix, dim3(b->n_jobs), dim3(256), 0, s, b->d_jobs, b->d_prefix);
         unsigned g = (unsigned)((b->total_bricks + 255) / 256);
@@ -380,7 +383,7 @@ rc_status rc::launch_batch_items(const RenderParams* items, const int* kinds, co
         cus[dev].store(n_cu, std::memory_order_relaxed);
     }
     const PersistKernel& k = persist_kernel(kind_mask);
-    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, s, counter);
     hipLaunchKernelGGL(k.fn, dim3((unsigned)(n_cu * 4 * k.waves)), dim3(64), (size_t)lds_bytes,
                        s, items, kinds, tile_off, order, n, total, counter, lds_bytes);
     RC_HIP(hipGetLastError());

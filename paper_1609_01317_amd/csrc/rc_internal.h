@@ -160,9 +160,15 @@ void fill_view(ViewParams& V, const rc_camera* cam);
 // in the product build)
 unsigned int* debug_counter();
 rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t st);
+// Work queues of the persistent batched kernel (persist.h): one per XCD,
+// their counters kQueueStride ints apart; kQueueGroup consecutive tiles per
+// group dealt to the queues round-robin.
+constexpr int kQueues = 8, kQueueGroup = 16, kQueueStride = 256;
+
 // The persistent batched kernel over n items already in device memory
 // (queue reset included); total = the items' tiles, kinds/order as in
-// rc_batch_create, kind_mask = the set of the items' kinds (bit per kind).
+// rc_batch_create, counter = kQueues * kQueueStride ints of device memory
+// for the work queues, kind_mask = the set of the items' kinds (bit per kind).
 rc_status launch_batch_items(const RenderParams* items, const int* kinds, const int* tile_off,
                              const int* order, int n, int total, int* counter, int lds_bytes,
                              unsigned kind_mask, hipStream_t s);

@@ -516,11 +516,14 @@ namespace rc {
 // ---------------------------------------------------------------- several views
 // Several views of one volume, table, shading and options in as few launches
 // as possible (up to kMaxViews views per launch).  The per-call scratch
-// holds the items of one launch, their kinds, tile offsets, order and the
-// work counter, then the skip masks.
+// holds the items of one launch, their kinds, tile offsets and order (one
+// 256-byte slot each, kViewsMetaBytes in all) and the work-queue counters,
+// then the skip masks.
+constexpr size_t kViewsMetaBytes = 1024;
+
 size_t views_scratch_bytes(const rc_volume* v, int tf_len, const rc_options* opt) {
     const size_t items_bytes = ((sizeof(RenderParams) * kMaxViews + 255) / 256) * 256;
-    const size_t queue_bytes = 256 * 4;
+    const size_t queue_bytes = kViewsMetaBytes + sizeof(int) * kQueues * kQueueStride;
     size_t mask_bytes = 0, super_bytes = 0, skip_bytes = 0;
     if (opt->skip_empty) skip_bytes = skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes);
     return items_bytes + queue_bytes + skip_bytes;
@@ -564,7 +567,7 @@ rc_status render_views_into(const rc_volume* v, const rc_camera* cams, int n_vie
                                                                 : kBatchWaveLdsBytes;
     P.box_bytes = lds_bytes;
     const size_t items_bytes = ((sizeof(RenderParams) * kMaxViews + 255) / 256) * 256;
-    const size_t queue_bytes = 256 * 4;
+    const size_t queue_bytes = kViewsMetaBytes + sizeof(int) * kQueues * kQueueStride;
     size_t mask_bytes = 0, super_bytes = 0;
     if (opt->skip_empty) (void)skip_scratch_bytes(v, tf_len, &mask_bytes, &super_bytes);
     char* base = scratch;
@@ -572,7 +575,7 @@ rc_status render_views_into(const rc_volume* v, const rc_camera* cams, int n_vie
     int* kinds = (int*)(base + items_bytes);
     int* tile_off = (int*)(base + items_bytes + 256);
     int* order = (int*)(base + items_bytes + 512);
-    int* counter = (int*)(base + items_bytes + 768);
+    int* counter = (int*)(base + items_bytes + kViewsMetaBytes);  // work-queue counters
     rc_status st = RC_OK;
     if (opt->skip_empty) {
         char* sk = base + items_bytes + queue_bytes;
