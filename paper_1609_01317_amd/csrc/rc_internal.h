@@ -163,7 +163,7 @@ rc_status launch_forward(const RenderParams& P, rc_dtype dt, int op, hipStream_t
 // Work queues of the persistent batched kernel (persist.h): one per XCD,
 // their counters kQueueStride ints apart; kQueueGroup consecutive tiles per
 // group dealt to the queues round-robin.
-constexpr int kQueues = 8, kQueueGroup = 16, kQueueStride = 256;
+constexpr int kQueues = 8, kQueueGroup = 8, kQueueStride = 256;
 
 // The persistent batched kernel over n items already in device memory
 // (queue reset included); total = the items' tiles, kinds/order as in

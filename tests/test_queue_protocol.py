@@ -2,8 +2,8 @@
 
 raycast_batch (csrc/persist.h) keeps resident waves that take work units
 from eight queues, one per XCD.  The launch's units are cut into groups of
-16 consecutive tiles dealt round-robin to the queues; entry i of queue q is
-unit ((i // 16) * 8 + q) * 16 + i % 16.  A wave fetches i = atomicAdd(
+8 consecutive tiles dealt round-robin to the queues; entry i of queue q is
+unit ((i // 8) * 8 + q) * 8 + i % 8.  A wave fetches i = atomicAdd(
 counter[q], 1) from the queue of its own XCD, leaves that queue when the
 unit of (unsigned)i lies beyond the launch, then does the same with the
 other seven in turn (skipping a queue whose counter it reads as already
@@ -33,7 +33,7 @@ import numpy as np
 import pytest
 
 INT_MIN = -(1 << 31)
-QUEUES, GROUP = 8, 16
+QUEUES, GROUP = 8, 8
 
 
 def _wrap(v, bits=32):
