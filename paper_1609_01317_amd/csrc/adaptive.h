@@ -75,8 +75,9 @@ __device__ __forceinline__ double adaptive_super_step(const RenderParams& P, con
         }
         unsigned f = kSuperEmpty | kSuperPoor | kSuperRich;
         if (lane < nsr) {
-            const int r0 = lane % sdim[0], r1 = (lane / sdim[0]) % sdim[1],
-                      r2 = lane / (sdim[0] * sdim[1]);
+            const int r01 = small_quot(lane, small_inv(sdim[0]));
+            const int r2 = small_quot(r01, small_inv(sdim[1]));
+            const int r0 = lane - r01 * sdim[0], r1 = r01 - r2 * sdim[1];
             f = to_gmem(P.super_empty)[RC_IDX(P.dbg,
                                      ((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0,
                                      (long long)P.nsx * P.nsy * P.nsz)];
@@ -206,8 +207,9 @@ __device__ inline void march_wave_adaptive(const RenderParams& P, const Ray& R, 
             all = nbr == 64 ? ~0ull : (1ull << nbr) - 1ull;
             bool lv = false, pr = false;
             if (lane < nbr) {
-                const int r0 = lane % ch.bdim[0], r1 = (lane / ch.bdim[0]) % ch.bdim[1],
-                          r2 = lane / (ch.bdim[0] * ch.bdim[1]);
+                const int r01 = small_quot(lane, small_inv(ch.bdim[0]));
+                const int r2 = small_quot(r01, small_inv(ch.bdim[1]));
+                const int r0 = lane - r01 * ch.bdim[0], r1 = r01 - r2 * ch.bdim[1];
                 const int b = ((ch.blo[2] + r2) * P.nby + ch.blo[1] + r1) * P.nbx + ch.blo[0] + r0;
                 pr = brick_poor(gload(P.range + RC_IDX(P.dbg, b, nbricks)), P.adapt_range);
                 lv = !P.skip || to_gmem(P.empty)[RC_IDX(P.dbg, b, nbricks)] == 0;

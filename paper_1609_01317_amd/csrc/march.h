@@ -33,6 +33,15 @@ __device__ __forceinline__ float lerpf(float a, float b, float t) { return fmaf(
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// n / d for 0 <= n, 1 <= d, n + d < 2^20 without an integer division:
+// (n + 1/2) / d lies at least 1 / (2d) from an integer, and the FP32 product
+// with the reciprocal (hardware rcp, within 1 ulp) is within 2^-21 of it
+// relatively, so truncation gives the exact quotient.
+__device__ __forceinline__ float small_inv(int d) { return __builtin_amdgcn_rcpf((float)d); }
+__device__ __forceinline__ int small_quot(int n, float inv_d) {
+    return (int)(((float)n + 0.5f) * inv_d);
+}
+
 // Device memory read through global (not flat) loads: a wait for them does
 // not also wait for the wave's LDS traffic, nor a wait for LDS for them.
 template <typename T>
@@ -686,11 +695,12 @@ __device__ inline void stage_box(const RenderParams& P, LT* lds, const int lo[3]
     const VT* vox = (const VT*)P.vox;
     const int gx = dim[0] >> 1, gy = dim[1] >> 1, gz = dim[2] >> 1;
     const int ncol = gx * gy;
+    const float inv_gx = small_inv(gx);
     const int xmax = P.nbx * 8, ymax = P.nby * 8, zmax = P.nbz * 8;
     const int bx = dim[0], bxy = dim[0] * dim[1];
     // each lane owns (x, y) columns of groups and walks them along z
     for (int col = lane; col < ncol; col += 64) {
-        int ix = col % gx, iy = col / gx;
+        const int iy = small_quot(col, inv_gx), ix = col - iy * gx;
         int x0 = lo[0] + 2 * ix, y0 = lo[1] + 2 * iy;
         bool xy_in = x0 >= 0 && y0 >= 0 && x0 + 1 < xmax && y0 + 1 < ymax;
         int oxy = xy_in ? off_x(x0) + off_y(y0, P.sy) : 0;
@@ -914,7 +924,9 @@ __device__ __forceinline__ bool super_chunk_empty(const RenderParams& P, const R
         }
         bool live = false;
         if (lane < nsr) {
-            int r0 = lane % sdim[0], r1 = (lane / sdim[0]) % sdim[1], r2 = lane / (sdim[0] * sdim[1]);
+            const int r01 = small_quot(lane, small_inv(sdim[0]));
+            const int r2 = small_quot(r01, small_inv(sdim[1]));
+            const int r0 = lane - r01 * sdim[0], r1 = r01 - r2 * sdim[1];
             live = (to_gmem(P.super_empty)[RC_IDX(P.dbg,
                                          ((slo[2] + r2) * P.nsy + slo[1] + r1) * P.nsx + slo[0] + r0,
                                          (long long)P.nsx * P.nsy * P.nsz)] & kSuperEmpty) == 0;
@@ -1047,8 +1059,9 @@ __device__ inline void march_wave(const RenderParams& P, const Ray& R, bool has_
             int nbr = ch.bdim[0] * ch.bdim[1] * ch.bdim[2];
             bool live = false;
             if (lane < nbr) {
-                int r0 = lane % ch.bdim[0], r1 = (lane / ch.bdim[0]) % ch.bdim[1],
-                    r2 = lane / (ch.bdim[0] * ch.bdim[1]);
+                const int r01 = small_quot(lane, small_inv(ch.bdim[0]));
+                const int r2 = small_quot(r01, small_inv(ch.bdim[1]));
+                const int r0 = lane - r01 * ch.bdim[0], r1 = r01 - r2 * ch.bdim[1];
                 int b = ((ch.blo[2] + r2) * P.nby + ch.blo[1] + r1) * P.nbx + ch.blo[0] + r0;
                 live = to_gmem(P.empty)[RC_IDX(P.dbg, b, (long long)P.nbx * P.nby * P.nbz)] == 0;
             }
