@@ -90,6 +90,34 @@ def test_batch_equals_single_renders(cfg):
         assert not bad.any(), err
 
 
+@pytest.mark.parametrize("images", [[(1, 1)], [(1, 1), (3, 2)], [(8, 8)] * 3 + [(9, 1)],
+                                    [(70, 9)] * 5])
+def test_batches_smaller_than_the_work_queues(images):
+    """The launch's tiles go to eight per-XCD queues in groups of 8: a batch
+    of one tile (seven queues empty from the start), a few tiles, and one
+    that fills some groups partly.  Every output equals rc_render bit for
+    bit; the pixels were all written (they start at -1)."""
+    sc = W.config_small(seed=51, dims=(21, 18, 16), dtype=np.uint16, image=(8, 8),
+                        op="sobel3d", ert=0.97, skip=True)
+    vol = gpu_volume(sc, bricks=True)
+    tf = to_dev(sc.tf)
+    items = []
+    for j, (w, h) in enumerate(images):
+        cam = W.orbit_camera((21, 18, 16), sc.spacing, 23.0 * j, 15.0, w, h)
+        items.append({"vol": vol, "camera": cam, "tf": tf, "shading": sc.shading,
+                      "options": sc.options,
+                      "out": torch.full((h, w, 4), -1.0, device="cuda"), "aux": rc.new_aux(cam)})
+    refs = _reference(items)
+    for cfg in (None, dict(tile_w=4, waves_per_wg=2, wg_per_cu=1, order=0)):
+        for it in items:
+            it["out"].fill_(-1.0)
+        rc.rc_render_batch(items, cfg)
+        torch.cuda.synchronize()
+        for it, (img, aux) in zip(items, refs):
+            assert torch.equal(it["out"], img)
+            assert torch.equal(it["aux"], aux)
+
+
 def test_items_sharing_volume_and_table():
     """Orbit-style batches: several views of one volume and table (their
     empty-brick masks are computed once and shared), mixed with items that
