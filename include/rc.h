@@ -275,8 +275,10 @@ rc_status rc_batch_create(const rc_batch_item* items, int n, const rc_batch_conf
 
 /* Render every item with one persistent launch (plus three small mask
  * kernels and a queue reset): resident waves take (item, tile) work from
- * a queue, which keeps the compute units fuller than one launch per image
- * (an orbit of many views renders faster this way than view by view).  use_graph = 1 captures that sequence into a
+ * eight work queues, one per XCD (neighbouring tiles stay on one XCD; a
+ * wave whose queue is empty takes from the others), which keeps the compute
+ * units fuller than one launch per image (an orbit of many views renders
+ * faster this way than view by view).  use_graph = 1 captures that sequence into a
  * HIP graph on the first call and replays it afterwards (stream must not be
  * NULL); use_graph = 0 launches eagerly.  Errors: RC_E_INVALID, RC_E_DEVICE. */
 rc_status rc_batch_render(rc_batch* b, int use_graph, void* stream);
