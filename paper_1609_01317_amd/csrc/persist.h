@@ -6,7 +6,7 @@
 // Work queues: one per XCD.  The launch's units (items in queue order, each
 // item's tiles row by row) are cut into groups of kQueueGroup consecutive
 // tiles, dealt round-robin to the kQueues queues: queue q holds groups q,
-// q + 8, ..., so an XCD renders strips of neighbouring tiles (neighbouring
+// q + kQueues, ..., so an XCD renders strips of neighbouring tiles (neighbouring
 // rays read the same voxels through that XCD's L2).  A wave takes units from
 // the queue of its own XCD (the hardware XCC id), one atomic add per unit,
 // and when that queue is empty from the others in turn; it leaves when all

@@ -32,28 +32,44 @@ rc_status hip_fail(hipError_t e, const char* what) {
 }
 
 // ---------------------------------------------------------------- kernels
-// One thread per voxel of the padded bricked array: voxel m of brick b
-// takes the source voxel at the clamped coordinates, so the padding
-// replicates the edge (Section 2.1: the grid is a 3D array of samples).
+// One workgroup per run of kTileRun bricks along x: the run's voxels (64
+// rows of kBrick * kTileRun voxels, contiguous along x in the source) are read row
+// by row at clamped coordinates, so the padding replicates the edge
+// (Section 2.1: the grid is a 3D array of samples), staged in LDS, and
+// written out brick by brick in Morton order: the run's bricks are
+// consecutive in the bricked array, so both the reads and the writes are
+// contiguous runs.  The staging rows are padded (kRunRow, kRunPlane) so the
+// 64 voxels a wave reads back in Morton order fall in distinct LDS banks.
+constexpr int kTileRun = 8;
+constexpr int kRunRow = kBrick * kTileRun + 4;
+constexpr int kRunPlane = kBrick * kRunRow + 16;
 template <typename T>
 __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* __restrict__ dst,
                                                   int nx, int ny, int nz, int nbx, int nby,
-                                                  long long total) {
-    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
-    long long b = idx >> 9;
-    uint32_t m = (uint32_t)(idx & 511);
-    int bx = (int)(b % nbx);
-    long long rest = b / nbx;
-    int by = (int)(rest % nby);
-    int bz = (int)(rest / nby);
-    int x = bx * kBrick + (int)compact3(m);
-    int y = by * kBrick + (int)compact3(m >> 1);
-    int z = bz * kBrick + (int)compact3(m >> 2);
-    x = min(x, nx - 1);
-    y = min(y, ny - 1);
-    z = min(z, nz - 1);
-    dst[idx] = src[((long long)z * ny + y) * nx + x];
+                                                  long long n_runs) {
+    __shared__ T run[kBrick * kRunPlane];      // voxel (x, y, z) of the run at z, y, x strides
+    const long long r = blockIdx.x;
+    if (r >= n_runs) return;
+    const int runs_x = (nbx + kTileRun - 1) / kTileRun;
+    const int rx = (int)(r % runs_x);
+    const long long rest = r / runs_x;
+    const int by = (int)(rest % nby), bz = (int)(rest / nby);
+    const int bx0 = rx * kTileRun, nb = min(kTileRun, nbx - bx0);
+    const int x0 = bx0 * kBrick, y0 = by * kBrick, z0 = bz * kBrick;
+    for (int i = threadIdx.x; i < kBrick * kBrick * kBrick * kTileRun; i += blockDim.x) {
+        const int xl = i % (kBrick * kTileRun), row = i / (kBrick * kTileRun);
+        if (xl >= kBrick * nb) continue;
+        const int x = min(x0 + xl, nx - 1), y = min(y0 + (row & 7), ny - 1),
+                  z = min(z0 + (row >> 3), nz - 1);
+        run[(row >> 3) * kRunPlane + (row & 7) * kRunRow + xl] = src[((long long)z * ny + y) * nx + x];
+    }
+    __syncthreads();
+    T* out = dst + (((long long)bz * nby + by) * nbx + bx0) * kBrickVox;
+    for (int i = threadIdx.x; i < kBrickVox * nb; i += blockDim.x) {
+        const uint32_t m = (uint32_t)(i & (kBrickVox - 1));
+        out[i] = run[(int)compact3(m >> 2) * kRunPlane + (int)compact3(m >> 1) * kRunRow +
+                     (i / kBrickVox) * kBrick + (int)compact3(m)];
+    }
 }
 
 // One wave per brick: min and max over voxels [b0, b0+8] per axis (the
@@ -89,8 +105,8 @@ __global__ __launch_bounds__(64) void brick_minmax(const T* __restrict__ vox, fl
 static int elem_size(rc_dtype dt) { return dt == RC_U8 ? 1 : dt == RC_U16 ? 2 : 4; }
 
 static rc_status launch_tile(rc_volume* v, const void* src, hipStream_t st) {
-    long long total = v->nbricks * kBrickVox;
-    unsigned grid = (unsigned)((total + 255) / 256);
+    const long long total = (long long)((v->nbx + kTileRun - 1) / kTileRun) * v->nby * v->nbz;
+    const unsigned grid = (unsigned)total;
     switch (v->dtype) {
         case RC_U8:
             hipLaunchKernelGGL(brick_tile<uint8_t>, dim3(grid), dim3(256), 0, st,
