@@ -28,8 +28,10 @@
  *    batch's descriptors, queue and masks (rc_batch_create; freed by
  *    rc_batch_destroy), and the per-call scratch of rc_render and
  *    rc_render_views (skip masks, counters, the views' item descriptors)
- *    as stream-ordered allocations on `stream` (hipMallocAsync, released
- *    with hipFreeAsync in the same call).
+ *    and the tile counter of the chunked reverse pass (rc_render_backward,
+ *    rc_render_backward_views with a shading model or a table over 2048
+ *    entries) as stream-ordered allocations on `stream` (hipMallocAsync,
+ *    released with hipFreeAsync in the same call).
  *  - Errors: every argument is checked on the host before anything is
  *    enqueued, so a failing call leaves no partial work.  A call returns a
  *    negative rc_status and rc_last_error() describes it.  Nothing aborts
@@ -209,7 +211,7 @@ rc_status rc_render(const rc_volume* vol, const rc_camera* cam, const float* tf_
  *   grad_tf_dev    device [tf_len][4] float32, accumulated (+=)
  * The march runs back to front from each ray's last sample and recovers the
  * transmittance from aux.t_final instead of storing per-sample state.
- * Errors: RC_E_INVALID, RC_E_DEVICE.
+ * Errors: RC_E_INVALID, RC_E_OOM, RC_E_DEVICE.
  */
 rc_status rc_render_backward(const rc_volume* vol, const rc_camera* cam, const float* tf_rgba_dev,
                              int tf_len, const rc_shading* sh, const rc_options* opt,

@@ -20,13 +20,15 @@ struct BackwardParams {
     unsigned int* dbg;      // bounds-checked build: violation counter; else null
     int box_bytes;          // LDS per wave of the chunked kernel (dV box + voxel box)
     int chunk_len;          // first chunk length of the chunked kernel, lattice steps; 0 = per-ray kernel
+    int* next_unit;         // the chunked kernel's tile counter, zero at launch
 };
 
 constexpr int kBwdTile = 8;               // 8x8 pixels, one wave per workgroup
 constexpr int kBwdLdsEntries = 2048;      // table sizes up to this are privatised in LDS
 constexpr int kBwdLdsTable = 1024;        // and up to this also read from LDS
 constexpr float kTinyT = 1e-30f;
-// The chunked kernel: blocks of kBwdBoxWaves waves (one tile each) share
+// The chunked kernel: resident blocks of kBwdBoxWaves waves (each wave
+// taking tiles one at a time from a counter) share
 // the table gradient in LDS -- tables up to kBwdBoxTfEntries entries, so a
 // whole block's samples, which mostly read a few hot entries, meet in LDS
 // instead of at a few device addresses -- and each wave has up to
@@ -544,55 +546,6 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
     }
     for (int i = lane; i < Bp.box_bytes / 4; i += 64) dvb[i] = 0.0f;
     __syncthreads();
-    // one tile per wave, in the work order of raycast_bwd
-    int b = 0, v = view_of_unit(S, 1, (int)blockIdx.x * kBwdBoxWaves + wave, b);
-    const ViewParams& V = S.v[v < 0 ? 0 : v];
-    int tiles_x = (V.W + kBwdTile - 1) / kBwdTile, tiles_y = (V.H + kBwdTile - 1) / kBwdTile;
-    int tx = centre_out(b % tiles_x, tiles_x), ty = centre_out(b / tiles_x, tiles_y);
-    int px = tx * kBwdTile + (lane % kBwdTile);
-    int py = ty * kBwdTile + (lane / kBwdTile);
-    const bool valid = v >= 0 && b < tiles_x * tiles_y && px < V.W && py < V.H;
-    Ray R;
-    R.K = -1;
-    R.t_in = R.t_out = 0.0;
-    for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = R.p0[a] = R.dp[a] = 0.0;
-    if (valid) setup_ray(P, V, px, py, R);
-    RayShade rs;
-    ray_shade(P, R, rs);
-    rc_aux ax{-1, 0.0f};
-    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (valid) {
-        long long pix = (long long)py * V.W + px;
-        ax = V.aux[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
-        g = V.grad[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
-    }
-    const int last = ax.k_last;
-    const bool has = valid && R.K >= 0 && last >= 0 && last <= R.K;
-    // Anchor: the last index a whose front transmittance T_a is at least
-    // kTinyT (see raycast_bwd).
-    int anchor = last + 1;
-    float Ta = ax.t_final;
-    if (has && !(Ta >= kTinyT)) {
-        float T = 1.0f;
-        anchor = 0;
-        for (int k = 0; k <= last; ++k) {
-            BwdSample Sx;
-            bwd_sample<VT, OP, LIT>(P, tab, R, rs, k, false, Sx);
-            float Tn = T * (1.0f - Sx.a);
-            if (!(Tn >= kTinyT)) break;
-            T = Tn;
-            anchor = k + 1;
-        }
-        Ta = T;
-    }
-    float Bk1[3] = {0.f, 0.f, 0.f};
-    float Pk1 = 1.0f, Q = 1.0f;
-    DtfRun run;
-    DvRun vrun;
-    int k = has ? last : -1;
-    const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
-                             (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
-    const DvSink glob{nullptr, {0, 0, 0}, 0, 0, 0};
     // This wave's LDS: the dV box grows from the start, the chunk's voxel box
     // sits at the end.  [0, zero_end) is known to be all zero; the dV box
     // must start zeroed, so where it grows into bytes a voxel box used it is
@@ -600,119 +553,180 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
     unsigned char* wl = (unsigned char*)dvb;
     const int wave_bytes = Bp.box_bytes;
     int zero_end = wave_bytes;
-    // Every chunk moves at least the lane that defines thi one sample on,
-    // so 64 (K_max + 1) chunks finish any wave; the cap only turns a broken
-    // invariant into a wrong gradient instead of a wave that never ends.
-    const long long chunk_cap = 64ll * (wave_max(has ? last : -1) + 2);
-    long long n_chunks = 0;
+    // Resident waves take the tiles in the work order of raycast_bwd from
+    // a counter, one atomic add per tile: a wave whose rays end early takes
+    // the next tile instead of holding its slot until the block's slowest
+    // ray ends, and the block's table gradient is flushed once.  The
+    // counter only grows, so each wave leaves at its first index past the
+    // tiles (compared unsigned: a bad start also ends the loop).
+    const unsigned n_units = (unsigned)S.block_off[S.n];
     for (;;) {
-        const bool active = k >= 0;
-        if (__ballot(active) == 0ull || ++n_chunks > chunk_cap) break;
-        const double thi = wave_max_nonneg(active ? R.t_in + (double)k * P.step : 0.0);
-        int len = Bp.chunk_len, kstop = k + 1;
-        DvSink sk = glob;
-        int vlo[3] = {0, 0, 0}, vdim[3] = {0, 0, 0}, vbytes = 0;
+        int fetched = 0;
+        if (lane == 0) fetched = atomicAdd(Bp.next_unit, 1);
+        const unsigned unit = (unsigned)__builtin_amdgcn_readfirstlane(__shfl(fetched, 0));
+        if (unit >= n_units) break;
+        int b = 0, v = view_of_unit(S, 1, (int)unit, b);
+        const ViewParams& V = S.v[v < 0 ? 0 : v];
+        int tiles_x = (V.W + kBwdTile - 1) / kBwdTile, tiles_y = (V.H + kBwdTile - 1) / kBwdTile;
+        int tx = centre_out(b % tiles_x, tiles_x), ty = centre_out(b / tiles_x, tiles_y);
+        int px = tx * kBwdTile + (lane % kBwdTile);
+        int py = ty * kBwdTile + (lane / kBwdTile);
+        const bool valid = v >= 0 && b < tiles_x * tiles_y && px < V.W && py < V.H;
+        Ray R;
+        R.K = -1;
+        R.t_in = R.t_out = 0.0;
+        for (int a = 0; a < 3; ++a) R.o[a] = R.d[a] = R.p0[a] = R.dp[a] = 0.0;
+        if (valid) setup_ray(P, V, px, py, R);
+        RayShade rs;
+        ray_shade(P, R, rs);
+        rc_aux ax{-1, 0.0f};
+        float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (valid) {
+            long long pix = (long long)py * V.W + px;
+            ax = V.aux[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
+            g = V.grad[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
+        }
+        const int last = ax.k_last;
+        const bool has = valid && R.K >= 0 && last >= 0 && last <= R.K;
+        // Anchor: the last index a whose front transmittance T_a is at least
+        // kTinyT (see raycast_bwd).
+        int anchor = last + 1;
+        float Ta = ax.t_final;
+        if (has && !(Ta >= kTinyT)) {
+            float T = 1.0f;
+            anchor = 0;
+            for (int k = 0; k <= last; ++k) {
+                BwdSample Sx;
+                bwd_sample<VT, OP, LIT>(P, tab, R, rs, k, false, Sx);
+                float Tn = T * (1.0f - Sx.a);
+                if (!(Tn >= kTinyT)) break;
+                T = Tn;
+                anchor = k + 1;
+            }
+            Ta = T;
+        }
+        float Bk1[3] = {0.f, 0.f, 0.f};
+        float Pk1 = 1.0f, Q = 1.0f;
+        DtfRun run;
+        DvRun vrun;
+        int k = has ? last : -1;
+        const GlobalSrc<VT> gsrc{(const VT*)P.vox, P.nx, P.ny, P.nz, P.sy, P.sz,
+                                 (long long)P.nbx * P.nby * P.nbz * 512, P.dbg};
+        const DvSink glob{nullptr, {0, 0, 0}, 0, 0, 0};
+        // Every chunk moves at least the lane that defines thi one sample on,
+        // so 64 (K_max + 1) chunks finish any wave; the cap only turns a broken
+        // invariant into a wrong gradient instead of a wave that never ends.
+        const long long chunk_cap = 64ll * (wave_max(has ? last : -1) + 2);
+        long long n_chunks = 0;
         for (;;) {
-            const double tlo = thi - (double)len * P.step;
-            int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
-            kstop = k + 1;
-            if (active) {
-                // first index past tlo (rounding here only groups the work)
-                const double q = floor((tlo - R.t_in) * P.inv_step) + 1.0;
-                kstop = q <= 0.0 ? 0 : (q > (double)k ? k + 1 : (int)q);
-                // the lane(s) that define thi always own their next sample
-                if (R.t_in + (double)k * P.step >= thi) kstop = min(kstop, k);
-                if (kstop <= k) {
-                    Cell c0, c1;
-                    double pv[3];
-                    lattice_point(P, R, kstop, c0, pv);
-                    lattice_point(P, R, k, c1, pv);
+            const bool active = k >= 0;
+            if (__ballot(active) == 0ull || ++n_chunks > chunk_cap) break;
+            const double thi = wave_max_nonneg(active ? R.t_in + (double)k * P.step : 0.0);
+            int len = Bp.chunk_len, kstop = k + 1;
+            DvSink sk = glob;
+            int vlo[3] = {0, 0, 0}, vdim[3] = {0, 0, 0}, vbytes = 0;
+            for (;;) {
+                const double tlo = thi - (double)len * P.step;
+                int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+                kstop = k + 1;
+                if (active) {
+                    // first index past tlo (rounding here only groups the work)
+                    const double q = floor((tlo - R.t_in) * P.inv_step) + 1.0;
+                    kstop = q <= 0.0 ? 0 : (q > (double)k ? k + 1 : (int)q);
+                    // the lane(s) that define thi always own their next sample
+                    if (R.t_in + (double)k * P.step >= thi) kstop = min(kstop, k);
+                    if (kstop <= k) {
+                        Cell c0, c1;
+                        double pv[3];
+                        lattice_point(P, R, kstop, c0, pv);
+                        lattice_point(P, R, k, c1, pv);
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        mn[a] = min(c0.c[a], c1.c[a]);
-                        mx[a] = max(c0.c[a], c1.c[a]);
+                        for (int a = 0; a < 3; ++a) {
+                            mn[a] = min(c0.c[a], c1.c[a]);
+                            mx[a] = max(c0.c[a], c1.c[a]);
+                        }
                     }
                 }
-            }
-            int lo[3], dim[3];
-            long long nvox = 1, vvox = 1;
+                int lo[3], dim[3];
+                long long nvox = 1, vvox = 1;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int cmin = wave_min(mn[a]), cmax = wave_max(mx[a]);
-                lo[a] = cmin - 1;                   // the taps reach one voxel below
-                dim[a] = cmax - cmin + 4;           // and two above the cells
-                nvox *= dim[a];
-                // the voxel box: the same span, widened to even bounds for
-                // the 2x2x2 group loads of stage_box
-                vlo[a] = lo[a] & ~1;
-                vdim[a] = ((cmax + 2) | 1) - vlo[a] + 1;
-                vvox *= vdim[a];
+                for (int a = 0; a < 3; ++a) {
+                    const int cmin = wave_min(mn[a]), cmax = wave_max(mx[a]);
+                    lo[a] = cmin - 1;                   // the taps reach one voxel below
+                    dim[a] = cmax - cmin + 4;           // and two above the cells
+                    nvox *= dim[a];
+                    // the voxel box: the same span, widened to even bounds for
+                    // the 2x2x2 group loads of stage_box
+                    vlo[a] = lo[a] & ~1;
+                    vdim[a] = ((cmax + 2) | 1) - vlo[a] + 1;
+                    vvox *= vdim[a];
+                }
+                const long long dvb16 = (nvox * 4 + 15) & ~15ll;
+                // unshaded samples read 8 voxels each: staging does not pay
+                // (measured); shaded ones read the operator's 64
+                const long long vb16 = LIT ? (vvox * (long long)sizeof(VT) + 15) & ~15ll : 0;
+                if (dvb16 + vb16 <= wave_bytes) {
+                    sk = DvSink{dvb, {lo[0], lo[1], lo[2]}, dim[0], dim[0] * dim[1], (int)nvox};
+                    vbytes = (int)vb16;
+                    break;
+                }
+                if (len <= 2) break;                    // read and scatter in device memory
+                len >>= 1;
             }
-            const long long dvb16 = (nvox * 4 + 15) & ~15ll;
-            // unshaded samples read 8 voxels each: staging does not pay
-            // (measured); shaded ones read the operator's 64
-            const long long vb16 = LIT ? (vvox * (long long)sizeof(VT) + 15) & ~15ll : 0;
-            if (dvb16 + vb16 <= wave_bytes) {
-                sk = DvSink{dvb, {lo[0], lo[1], lo[2]}, dim[0], dim[0] * dim[1], (int)nvox};
-                vbytes = (int)vb16;
-                break;
+            const VT* vbox = nullptr;
+            if (sk.lds && !LIT) {
+                if (zero_end < sk.n * 4) {
+                    for (int i = zero_end / 4 + lane; i < sk.n; i += 64) dvb[i] = 0.0f;
+                    zero_end = sk.n * 4;
+                }
+                wave_lds_sync();
+            } else if (sk.lds) {
+                if (zero_end < sk.n * 4) {
+                    for (int i = zero_end / 4 + lane; i < sk.n; i += 64) dvb[i] = 0.0f;
+                    zero_end = sk.n * 4;
+                }
+                VT* vb = (VT*)(wl + wave_bytes - vbytes);
+                stage_box<VT, VT>(P, vb, vlo, vdim, lane);
+                zero_end = min(zero_end, wave_bytes - vbytes);
+                wave_lds_sync();
+                vbox = vb;
             }
-            if (len <= 2) break;                    // read and scatter in device memory
-            len >>= 1;
+            const LdsSrc<VT> lsrc{vbox, {vlo[0], vlo[1], vlo[2]}, vdim[0], vdim[0] * vdim[1],
+                                  vdim[0] * vdim[1] * vdim[2], P.dbg};
+            // this lane's samples k .. kstop, back to front, read from the box
+            // (every one of them lies in it: their cells lie between the end
+            // cells the box was built from) or from the bricked volume
+            while (k >= kstop) {
+                BwdSample Sm;
+                float cn[8];
+                if (vbox) {
+                    bwd_fetch_from<VT>(P, R, k, lsrc, Sm, cn);
+                    bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm, vbox);
+                } else {
+                    bwd_fetch_from<VT>(P, R, k, gsrc, Sm, cn);
+                    bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm);
+                }
+                const float om = 1.0f - Sm.a;
+                if (k < anchor) {
+                    Q *= om;
+                    const float Tk = Q > 0.0f ? Ta / Q : 0.0f;
+                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, vrun, sk, Sm, rs, Tk, g, Bk1, Pk1);
+                }
+                Bk1[0] = fmaf(Sm.a, Sm.c[0], om * Bk1[0]);
+                Bk1[1] = fmaf(Sm.a, Sm.c[1], om * Bk1[1]);
+                Bk1[2] = fmaf(Sm.a, Sm.c[2], om * Bk1[2]);
+                Pk1 *= om;
+                --k;
+            }
+            dv_flush(P, Bp, sk, vrun);              // a cell run does not outlive its chunk
+            if (sk.lds) {
+                wave_lds_sync();
+                dv_box_flush(P, Bp, sk, lane);
+                wave_lds_sync();
+            }
         }
-        const VT* vbox = nullptr;
-        if (sk.lds && !LIT) {
-            if (zero_end < sk.n * 4) {
-                for (int i = zero_end / 4 + lane; i < sk.n; i += 64) dvb[i] = 0.0f;
-                zero_end = sk.n * 4;
-            }
-            wave_lds_sync();
-        } else if (sk.lds) {
-            if (zero_end < sk.n * 4) {
-                for (int i = zero_end / 4 + lane; i < sk.n; i += 64) dvb[i] = 0.0f;
-                zero_end = sk.n * 4;
-            }
-            VT* vb = (VT*)(wl + wave_bytes - vbytes);
-            stage_box<VT, VT>(P, vb, vlo, vdim, lane);
-            zero_end = min(zero_end, wave_bytes - vbytes);
-            wave_lds_sync();
-            vbox = vb;
-        }
-        const LdsSrc<VT> lsrc{vbox, {vlo[0], vlo[1], vlo[2]}, vdim[0], vdim[0] * vdim[1],
-                              vdim[0] * vdim[1] * vdim[2], P.dbg};
-        // this lane's samples k .. kstop, back to front, read from the box
-        // (every one of them lies in it: their cells lie between the end
-        // cells the box was built from) or from the bricked volume
-        while (k >= kstop) {
-            BwdSample Sm;
-            float cn[8];
-            if (vbox) {
-                bwd_fetch_from<VT>(P, R, k, lsrc, Sm, cn);
-                bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm, vbox);
-            } else {
-                bwd_fetch_from<VT>(P, R, k, gsrc, Sm, cn);
-                bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sm);
-            }
-            const float om = 1.0f - Sm.a;
-            if (k < anchor) {
-                Q *= om;
-                const float Tk = Q > 0.0f ? Ta / Q : 0.0f;
-                bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, vrun, sk, Sm, rs, Tk, g, Bk1, Pk1);
-            }
-            Bk1[0] = fmaf(Sm.a, Sm.c[0], om * Bk1[0]);
-            Bk1[1] = fmaf(Sm.a, Sm.c[1], om * Bk1[1]);
-            Bk1[2] = fmaf(Sm.a, Sm.c[2], om * Bk1[2]);
-            Pk1 *= om;
-            --k;
-        }
-        dv_flush(P, Bp, sk, vrun);              // a cell run does not outlive its chunk
-        if (sk.lds) {
-            wave_lds_sync();
-            dv_box_flush(P, Bp, sk, lane);
-            wave_lds_sync();
-        }
+        dtf_flush(P, Bp, lds, run);
     }
-    dtf_flush(P, Bp, lds, run);
     if (Bp.lds_tf) {
         __syncthreads();
         for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) {
@@ -722,26 +736,40 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
     }
 }
 
+__global__ void bwd_reset(int* next_unit) {
+    if (threadIdx.x == 0) *next_unit = 0;
+}
+
 template <typename VT>
-static void launch_bwd_t(const RenderParams& P, const ViewSet& S, const BackwardParams& Bp, int op,
-                         dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+static rc_status launch_bwd_t(const RenderParams& P, const ViewSet& S, const BackwardParams& Bp,
+                              int op, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    using BwdFn = void (*)(RenderParams, ViewSet, BackwardParams);
+    BwdFn fn;
     if (P.shade == RC_SHADE_NONE) {
-        if (Bp.chunk_len > 0)
-            hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s,
-                               P, S, Bp);
-        else
+        if (Bp.chunk_len == 0) {
             hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s, P,
                                S, Bp);
+            return RC_OK;
+        }
+        fn = raycast_bwd_box<VT, RC_GRAD_CENTRAL, false>;
     } else if (op == RC_GRAD_CENTRAL) {
-        hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_CENTRAL, true>), grid, block, lds, s, P, S,
-                           Bp);
+        fn = raycast_bwd_box<VT, RC_GRAD_CENTRAL, true>;
     } else if (op == RC_GRAD_SOBEL3D) {
-        hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_SOBEL3D, true>), grid, block, lds, s, P, S,
-                           Bp);
+        fn = raycast_bwd_box<VT, RC_GRAD_SOBEL3D, true>;
     } else {
-        hipLaunchKernelGGL((raycast_bwd_box<VT, RC_GRAD_ZUCKER_HUMMEL, true>), grid, block, lds, s,
-                           P, S, Bp);
+        fn = raycast_bwd_box<VT, RC_GRAD_ZUCKER_HUMMEL, true>;
     }
+    // the chunked kernel's waves walk the tiles: launch what stays resident
+    int dev = 0, n_cu = 0, per_cu = 0;
+    RC_HIP(hipGetDevice(&dev));
+    RC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    RC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn,
+                                                        (int)block.x, lds));
+    const unsigned resident = (unsigned)(std::max(1, n_cu) * std::max(1, per_cu));
+    grid.x = std::min(grid.x, resident);
+    hipLaunchKernelGGL(bwd_reset, dim3(1), dim3(64), 0, s, Bp.next_unit);
+    hipLaunchKernelGGL(fn, grid, block, lds, s, P, S, Bp);
+    return RC_OK;
 }
 
 }  // namespace rc
@@ -803,7 +831,12 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
         Bp.chunk_len = 0;
         lds = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 16;
     }
-    for (int first = 0; first < n_views; first += kMaxViews) {
+    // the chunked kernel's tile counter: a stream-ordered allocation, zeroed
+    // by a small kernel before each launch
+    Bp.next_unit = nullptr;
+    if (boxed) RC_HIP(hipMallocAsync((void**)&Bp.next_unit, 256, s));
+    rc_status st = RC_OK;
+    for (int first = 0; st == RC_OK && first < n_views; first += kMaxViews) {
         ViewSet S;
         S.n = n_views - first < kMaxViews ? n_views - first : kMaxViews;
         int off = 0;
@@ -818,12 +851,19 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
         S.block_off[S.n] = off;
         dim3 grid((unsigned)((off + waves - 1) / waves)), block(kBwdTile * kBwdTile * waves);
         int op = opt->gradient_op;
-        if (v->dtype == RC_U8) launch_bwd_t<uint8_t>(P, S, Bp, op, grid, block, lds, s);
-        else if (v->dtype == RC_U16) launch_bwd_t<uint16_t>(P, S, Bp, op, grid, block, lds, s);
-        else launch_bwd_t<float>(P, S, Bp, op, grid, block, lds, s);
-        RC_HIP(hipGetLastError());
+        if (v->dtype == RC_U8) st = launch_bwd_t<uint8_t>(P, S, Bp, op, grid, block, lds, s);
+        else if (v->dtype == RC_U16) st = launch_bwd_t<uint16_t>(P, S, Bp, op, grid, block, lds, s);
+        else st = launch_bwd_t<float>(P, S, Bp, op, grid, block, lds, s);
+        if (st == RC_OK) {
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) st = hip_fail(e, "reverse-pass launch");
+        }
     }
-    return RC_OK;
+    if (Bp.next_unit) {
+        hipError_t e = hipFreeAsync(Bp.next_unit, s);
+        if (st == RC_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync");
+    }
+    return st;
 }
 
 extern "C" rc_status rc_render_backward(const rc_volume* v, const rc_camera* cam,
