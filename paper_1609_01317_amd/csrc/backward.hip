@@ -154,7 +154,7 @@ __device__ __forceinline__ void bwd_finish(const RenderParams& P, const float4* 
     }
     S.c[0] = S.rgba.x; S.c[1] = S.rgba.y; S.c[2] = S.rgba.z;
     if (LIT && lit) {
-        gradient_exact<VT, OP>(P, base, S.ox, S.oy, S.oz, S.C, S.g);
+        gradient_exact<VT, OP>(P, base, S.ox, S.oy, S.oz, S.C, corner, S.g);
         shade(P, S.rgba, S.g, S.pv, rs, S.c);
     }
 }

@@ -111,11 +111,12 @@ __device__ __forceinline__ void voxel_stencil(const PlaneP<typename StencilT<VT,
 // Gradient at the point of cell C from the 4x4x4 footprint of ox/oy/oz in
 // the bricked volume: the operator at each of the cell's 8 corners, then
 // their trilinear blend (x, then y, then z), scaled to normalised value per
-// world unit like the forward.
+// world unit like the forward.  corner: the cell's own 8 voxels as the
+// value path read them (x + 2y + 4z), exact in FP32 for every volume type.
 template <typename VT, int OP>
 __device__ __forceinline__ void gradient_exact(const RenderParams& P, const VT* base,
                                                const int ox[4], const int oy[4], const int oz[4],
-                                               const Cell& C, float g[3]) {
+                                               const Cell& C, const float corner[8], float g[3]) {
     using DT = typename StencilT<VT, OP>::DT;
     using WT = typename StencilT<VT, OP>::WT;
     DT f[4][4][4];              // [z][y][x] of the footprint
@@ -128,7 +129,10 @@ __device__ __forceinline__ void gradient_exact(const RenderParams& P, const VT* 
                 // central differences never read the footprint's edges
                 const bool used = OpTaps<OP>::kSep || (x == 1 || x == 2) + (y == 1 || y == 2) +
                                                           (z == 1 || z == 2) >= 2;
-                f[z][y][x] = used ? (DT)base[ox[x] + oy[y] + oz[z]] : (DT)0;
+                const bool inner = (x == 1 || x == 2) && (y == 1 || y == 2) && (z == 1 || z == 2);
+                f[z][y][x] = inner  ? (DT)corner[(z - 1) * 4 + (y - 1) * 2 + (x - 1)]
+                             : used ? (DT)base[ox[x] + oy[y] + oz[z]]
+                                    : (DT)0;
             }
     // plane partials of the 4 corner columns on the 4 planes
     PlaneP<WT> pp[4][2][2];

@@ -213,9 +213,10 @@ def test_c5_crop_matches_finite_differences(c5):
 
 
 # ---------------------------------------------------------------- several views, one launch
-def _views_scene(n_views, seed=61, image=(40, 36)):
-    sc = W.config_small(seed=seed, dims=(21, 19, 17), dtype=np.float32, image=image,
-                        shading="none")
+def _views_scene(n_views, seed=61, image=(40, 36), dtype=np.float32, shading="none",
+                 op="central"):
+    sc = W.config_small(seed=seed, dims=(21, 19, 17), dtype=dtype, image=image,
+                        shading=shading, op=op)
     cams = [W.orbit_camera((21, 19, 17), sc.spacing, 17.0 * i, 25.0 - 3 * i, image[0], image[1])
             for i in range(n_views)]
     return sc, cams
@@ -246,8 +247,16 @@ def test_render_views_equals_single_renders(seed, dtype, op, shading, n_views, s
         assert torch.equal(o, ref) and torch.equal(a, a1)
 
 
-def test_backward_views_equals_sum_of_single_views():
-    sc, cams = _views_scene(18)
+@pytest.mark.parametrize("dtype,shading,op", [(np.float32, "none", "central"),
+                                              (np.uint16, "none", "central"),
+                                              (np.uint8, "blinn_phong", "sobel3d")])
+def test_backward_views_equals_sum_of_single_views(dtype, shading, op):
+    """18 views: two reverse launches of at most 16 views each, against one
+    rc_render_backward per view.  Unshaded with a 256-entry table takes the
+    per-ray kernel; the 4096-entry table of u16 volumes and a shading model
+    take the chunked kernel, whose tile counter is zeroed before each
+    launch."""
+    sc, cams = _views_scene(18, dtype=dtype, shading=shading, op=op)
     vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
     tf = to_dev(sc.tf)
     auxes = [rc.new_aux(c) for c in cams]
@@ -260,8 +269,11 @@ def test_backward_views_equals_sum_of_single_views():
     for c, a, g in zip(cams, auxes, grads):
         rc.rc_render_backward(vol, c, tf, sc.shading, sc.options, a, g, gv1, gt1)
     torch.cuda.synchronize()
-    assert _rel(gv.cpu().numpy(), gv1.cpu().numpy()) <= 1e-5
-    assert _rel(gt.cpu().numpy(), gt1.cpu().numpy()) <= 1e-5
+    a, b = gv.cpu().numpy().astype(np.float64), gv1.cpu().numpy().astype(np.float64)
+    c, d = gt.cpu().numpy().astype(np.float64), gt1.cpu().numpy().astype(np.float64)
+    assert np.abs(b).max() > 0 and np.abs(d).max() > 0
+    assert _rel(a, b) <= 1e-5 and _rel(c, d) <= 1e-5
+    assert _ok(a, b, c, d, "views vs single")
 
 
 def test_render_views_fn_matches_oracle():
