@@ -28,10 +28,9 @@
  *    batch's descriptors, queue and masks (rc_batch_create; freed by
  *    rc_batch_destroy), and the per-call scratch of rc_render and
  *    rc_render_views (skip masks, counters, the views' item descriptors)
- *    and the tile counter of the chunked reverse pass (rc_render_backward,
- *    rc_render_backward_views with a shading model or a table over 2048
- *    entries) as stream-ordered allocations on `stream` (hipMallocAsync,
- *    released with hipFreeAsync in the same call).
+ *    and the reverse pass's tile counter (rc_render_backward,
+ *    rc_render_backward_views) as stream-ordered allocations on `stream`
+ *    (hipMallocAsync, released with hipFreeAsync in the same call).
  *  - Errors: every argument is checked on the host before anything is
  *    enqueued, so a failing call leaves no partial work.  A call returns a
  *    negative rc_status and rc_last_error() describes it.  Nothing aborts

@@ -1,4 +1,4 @@
-// Reverse mode of the render: one ray per thread marches back to front
+// Reverse mode of the render: one ray per lane marches back to front
 // from its last composited sample and accumulates dL/dvolume and
 // dL/dtable, through the lighting and the gradient operator's taps when a
 // shading model is on.  No per-sample state is stored by the forward pass; the
@@ -19,15 +19,14 @@ struct BackwardParams {
     int M4;                 // table entries * 4 (the dTF length)
     unsigned int* dbg;      // bounds-checked build: violation counter; else null
     int box_bytes;          // LDS per wave of the chunked kernel (dV box + voxel box)
-    int chunk_len;          // first chunk length of the chunked kernel, lattice steps; 0 = per-ray kernel
+    int chunk_len;          // first chunk length, lattice steps
     int* next_unit;         // the chunked kernel's tile counter, zero at launch
 };
 
-constexpr int kBwdTile = 8;               // 8x8 pixels, one wave per workgroup
-constexpr int kBwdLdsEntries = 2048;      // table sizes up to this are privatised in LDS
-constexpr int kBwdLdsTable = 1024;        // and up to this also read from LDS
+constexpr int kBwdTile = 8;               // 8x8 pixels, one wave per tile
+constexpr int kBwdLdsTable = 1024;        // tables up to this are read from an LDS copy
 constexpr float kTinyT = 1e-30f;
-// The chunked kernel: resident blocks of kBwdBoxWaves waves (each wave
+// The reverse kernel: resident blocks of kBwdBoxWaves waves (each wave
 // taking tiles one at a time from a counter) share
 // the table gradient in LDS -- tables up to kBwdBoxTfEntries entries, so a
 // whole block's samples, which mostly read a few hot entries, meet in LDS
@@ -367,107 +366,6 @@ __device__ __forceinline__ void bwd_accumulate(const RenderParams& P, const Back
     dv_add(P, Bp, sk, vrun, S.C, dv);
 }
 
-// One workgroup = one wave = one 8x8 pixel tile of one view (work order:
-// view_of_unit / centre_out).  One-wave workgroups measured 18 % faster
-// than 16x16 tiles of four waves: a workgroup holds its slot until its
-// slowest ray ends, and the rays are serial chains of very different
-// length.  LIT: a shading model is on (the unshaded kernel carries none of
-// the lighting and stencil registers).
-template <typename VT, int OP, bool LIT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIT ? 1 : 4))) void
-raycast_bwd(RenderParams P, ViewSet S, BackwardParams Bp) {
-    extern __shared__ float lds[];
-    const float4* tab = P.tf;
-    if (Bp.lds_tf)
-        for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) lds[i] = 0.0f;
-    if (Bp.lds_table) {
-        float4* t = (float4*)(lds + (Bp.lds_tf ? P.M * 4 : 0));
-        for (int i = threadIdx.x; i < P.M; i += blockDim.x) t[i] = P.tf[i];
-        tab = t;
-    }
-    if (Bp.lds_tf || Bp.lds_table) __syncthreads();
-    // views take turns block by block, each view's tiles centre-out (the
-    // grid holds exactly the views' blocks, so every block finds its tile)
-    int b = 0, v = view_of_unit(S, 1, (int)blockIdx.x, b);
-    const ViewParams& V = S.v[v < 0 ? 0 : v];
-    int tiles_x = (V.W + kBwdTile - 1) / kBwdTile, tiles_y = (V.H + kBwdTile - 1) / kBwdTile;
-    int tx = centre_out(b % tiles_x, tiles_x), ty = centre_out(b / tiles_x, tiles_y);
-    int px = tx * kBwdTile + (threadIdx.x % kBwdTile);
-    int py = ty * kBwdTile + (threadIdx.x / kBwdTile);
-    if (v >= 0 && b < tiles_x * tiles_y && px < V.W && py < V.H) {
-        Ray R;
-        setup_ray(P, V, px, py, R);
-        RayShade rs;
-        ray_shade(P, R, rs);
-        long long pix = (long long)py * V.W + px;
-        rc_aux ax = V.aux[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
-        float4 g = V.grad[RC_IDX(P.dbg, pix, (long long)V.W * V.H)];
-        int last = ax.k_last;
-        if (R.K >= 0 && last >= 0 && last <= R.K) {
-            // Anchor: the last index a whose front transmittance T_a is at
-            // least kTinyT.  Normally a = last + 1 with T_a = t_final; if the
-            // ray went (nearly) opaque, a forward pass finds a instead.
-            int anchor = last + 1;
-            float Ta = ax.t_final;
-            if (!(Ta >= kTinyT)) {
-                float T = 1.0f;
-                anchor = 0;
-                for (int k = 0; k <= last; ++k) {
-                    BwdSample S;
-                    bwd_sample<VT, OP, LIT>(P, tab, R, rs, k, false, S);
-                    float Tn = T * (1.0f - S.a);
-                    if (!(Tn >= kTinyT)) break;
-                    T = Tn;
-                    anchor = k + 1;
-                }
-                Ta = T;
-            }
-            float Bk1[3] = {0.f, 0.f, 0.f};
-            float Pk1 = 1.0f;       // prod over samples behind k of (1 - a)
-            float Q = 1.0f;         // prod over samples k .. anchor-1 of (1 - a)
-            // unshaded: one sample ahead, the voxels of sample k-1 are in
-            // flight while sample k is accumulated (the shaded path re-reads
-            // 64 voxels per sample and keeps no second sample in registers)
-            BwdSample S, Sn;
-            float corner[8], cn[8];
-            DtfRun run;
-            DvRun vrun;
-            const DvSink glob{nullptr, {0, 0, 0}, 0, 0, 0};
-            bwd_fetch<VT>(P, R, last, S, corner);
-            bwd_finish<VT, OP, LIT>(P, tab, rs, true, corner, S);
-            for (int k = last; k >= 0; --k) {
-                if (!LIT && k > 0) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
-                float om = 1.0f - S.a;
-                if (k < anchor) {
-                    Q *= om;
-                    float Tk = Q > 0.0f ? Ta / Q : 0.0f;
-                    bwd_accumulate<VT, OP, LIT>(P, Bp, lds, run, vrun, glob, S, rs, Tk, g, Bk1,
-                                                Pk1);
-                }
-                Bk1[0] = fmaf(S.a, S.c[0], om * Bk1[0]);
-                Bk1[1] = fmaf(S.a, S.c[1], om * Bk1[1]);
-                Bk1[2] = fmaf(S.a, S.c[2], om * Bk1[2]);
-                Pk1 *= om;
-                if (k > 0) {
-                    if (LIT) bwd_fetch<VT>(P, R, k - 1, Sn, cn);
-                    bwd_finish<VT, OP, LIT>(P, tab, rs, true, cn, Sn);
-                    S = Sn;
-                }
-            }
-            dtf_flush(P, Bp, lds, run);
-            dv_flush(P, Bp, glob, vrun);
-        }
-    }
-    if (Bp.lds_tf) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < P.M * 4; i += blockDim.x) {
-            float v = lds[i];
-            if (v != 0.0f) unsafeAtomicAdd(&Bp.dtf[i], v);
-        }
-    }
-}
-
-
 // Maximum of non-negative doubles over the wave, exact: their bit patterns
 // order like unsigned 64-bit integers (0 is the identity for lanes a DPP
 // move does not write).
@@ -516,17 +414,18 @@ __device__ __forceinline__ void dv_box_flush(const RenderParams& P, const Backwa
     }
 }
 
-// The reverse march in chunks shared by the wave, for renders whose samples
-// scatter many contributions (the shaded reverse: up to 64 voxels per
-// sample through the operator's taps).  Each lane still runs its own ray
-// back to front; the wave only agrees on a window of ray parameter
-// (thi - len step, thi], thi = the latest pending sample of any lane, and
-// every lane processes its samples inside it.  Their contributions to dV go
-// to an LDS box over the window's voxels (LDS atomics), which is added to
-// dV once per chunk: one device atomic per touched voxel instead of one per
-// tap and sample.  A window whose box does not fit even at 2 steps sends
-// its contributions straight to dV.  Same work order and per-ray arithmetic
-// as raycast_bwd.
+// The reverse march in chunks shared by the wave.  A wave renders one 8x8
+// pixel tile at a time; each lane runs its own ray back to front, and the
+// wave only agrees on a window of ray parameter (thi - len step, thi],
+// thi = the latest pending sample of any lane, in which every lane
+// processes its samples.  Their contributions to dV go to an LDS box over
+// the window's voxels (LDS atomics), which is added to dV once per chunk:
+// one device atomic per touched voxel instead of one per tap (up to 64 per
+// shaded sample) or corner and sample.  A window whose box does not fit even
+// at 2 steps sends its contributions straight to dV.  Shaded renders also
+// stage the window's voxels in LDS (the operator reads 64 per sample).
+// Work order (view_of_unit, centre_out): views take turns, each view's
+// tiles centre-out, so the long rays through the middle start first.
 template <typename VT, int OP, bool LIT>
 __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParams P, ViewSet S,
                                                                     BackwardParams Bp) {
@@ -553,8 +452,8 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
     unsigned char* wl = (unsigned char*)dvb;
     const int wave_bytes = Bp.box_bytes;
     int zero_end = wave_bytes;
-    // Resident waves take the tiles in the work order of raycast_bwd from
-    // a counter, one atomic add per tile: a wave whose rays end early takes
+    // Resident waves take the tiles in that work order from a counter, one
+    // atomic add per tile: a wave whose rays end early takes
     // the next tile instead of holding its slot until the block's slowest
     // ray ends, and the block's table gradient is flushed once.  The
     // counter only grows, so each wave leaves at its first index past the
@@ -589,7 +488,9 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
         const int last = ax.k_last;
         const bool has = valid && R.K >= 0 && last >= 0 && last <= R.K;
         // Anchor: the last index a whose front transmittance T_a is at least
-        // kTinyT (see raycast_bwd).
+        // kTinyT.  Normally a = last + 1 with T_a = t_final; if the ray went
+        // (nearly) opaque, a forward pass finds a instead.  Samples from a on
+        // are composited but get no gradient (their T is below kTinyT).
         int anchor = last + 1;
         float Ta = ax.t_final;
         if (has && !(Ta >= kTinyT)) {
@@ -746,11 +647,6 @@ static rc_status launch_bwd_t(const RenderParams& P, const ViewSet& S, const Bac
     using BwdFn = void (*)(RenderParams, ViewSet, BackwardParams);
     BwdFn fn;
     if (P.shade == RC_SHADE_NONE) {
-        if (Bp.chunk_len == 0) {
-            hipLaunchKernelGGL((raycast_bwd<VT, RC_GRAD_CENTRAL, false>), grid, block, lds, s, P,
-                               S, Bp);
-            return RC_OK;
-        }
         fn = raycast_bwd_box<VT, RC_GRAD_CENTRAL, false>;
     } else if (op == RC_GRAD_CENTRAL) {
         fn = raycast_bwd_box<VT, RC_GRAD_CENTRAL, true>;
@@ -759,7 +655,7 @@ static rc_status launch_bwd_t(const RenderParams& P, const ViewSet& S, const Bac
     } else {
         fn = raycast_bwd_box<VT, RC_GRAD_ZUCKER_HUMMEL, true>;
     }
-    // the chunked kernel's waves walk the tiles: launch what stays resident
+    // the waves take tiles from the counter: launch what stays resident
     int dev = 0, n_cu = 0, per_cu = 0;
     RC_HIP(hipGetDevice(&dev));
     RC_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -799,42 +695,29 @@ static rc_status backward_views(const rc_volume* v, const rc_camera* cams, int n
     Bp.dtf = grad_tf_dev;
     Bp.M4 = tf_len * 4;
     Bp.dbg = P.dbg;
-    // Shaded renders scatter up to 64 voxels per sample, and tables beyond
-    // kBwdLdsEntries cannot be privatised per one-wave block: both go to the
-    // chunked kernel (LDS dV boxes, a table gradient shared by 8 waves).
-    // Unshaded renders with smaller tables keep the per-ray kernel.
-    const bool boxed = sh->model != RC_SHADE_NONE || tf_len > kBwdLdsEntries;
-    size_t lds = 0;
-    int waves = 1;
-    if (boxed) {
-        // LDS a block may take on this device (160 KiB on gfx950)
-        int dev = 0, lds_max = 0;
-        RC_HIP(hipGetDevice(&dev));
-        RC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        const size_t budget = (size_t)std::min(lds_max, kBwdLdsBytes);
-        waves = kBwdBoxWaves;
-        Bp.lds_tf = tf_len <= kBwdBoxTfEntries && (size_t)tf_len * 16 + 4096 <= budget;
-        Bp.lds_table = tf_len <= kBwdLdsTable;
-        size_t tf_bytes = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 16;
-        if (tf_bytes + 4096 > budget) {     // no room for the table copy: read it from memory
-            Bp.lds_table = 0;
-            tf_bytes = (Bp.lds_tf ? 1 : 0) * (size_t)tf_len * 16;
-        }
-        Bp.box_bytes = (int)(std::min<size_t>(kBwdBoxBytes, (budget - tf_bytes) / kBwdBoxWaves) &
-                             ~(size_t)15);
-        Bp.chunk_len = kBwdChunk;
-        lds = tf_bytes + (size_t)Bp.box_bytes * kBwdBoxWaves;
-    } else {
-        Bp.lds_tf = tf_len <= kBwdLdsEntries;
-        Bp.lds_table = tf_len <= kBwdLdsTable;
-        Bp.box_bytes = 0;
-        Bp.chunk_len = 0;
-        lds = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 16;
+    // LDS a block may take on this device (160 KiB on gfx950): the table
+    // gradient shared by the block's waves (tables up to kBwdBoxTfEntries),
+    // the table itself for small tables, and per wave its dV and voxel boxes
+    int dev = 0, lds_max = 0;
+    RC_HIP(hipGetDevice(&dev));
+    RC_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t budget = (size_t)std::min(lds_max, kBwdLdsBytes);
+    const int waves = kBwdBoxWaves;
+    Bp.lds_tf = tf_len <= kBwdBoxTfEntries && (size_t)tf_len * 16 + 4096 <= budget;
+    Bp.lds_table = tf_len <= kBwdLdsTable;
+    size_t tf_bytes = ((Bp.lds_tf ? 1 : 0) + (Bp.lds_table ? 1 : 0)) * (size_t)tf_len * 16;
+    if (tf_bytes + 4096 > budget) {     // no room for the table copy: read it from memory
+        Bp.lds_table = 0;
+        tf_bytes = (Bp.lds_tf ? 1 : 0) * (size_t)tf_len * 16;
     }
-    // the chunked kernel's tile counter: a stream-ordered allocation, zeroed
-    // by a small kernel before each launch
+    Bp.box_bytes = (int)(std::min<size_t>(kBwdBoxBytes, (budget - tf_bytes) / kBwdBoxWaves) &
+                         ~(size_t)15);
+    Bp.chunk_len = kBwdChunk;
+    const size_t lds = tf_bytes + (size_t)Bp.box_bytes * kBwdBoxWaves;
+    // the tile counter: a stream-ordered allocation, zeroed by a small kernel
+    // before each launch
     Bp.next_unit = nullptr;
-    if (boxed) RC_HIP(hipMallocAsync((void**)&Bp.next_unit, 256, s));
+    RC_HIP(hipMallocAsync((void**)&Bp.next_unit, 256, s));
     rc_status st = RC_OK;
     for (int first = 0; st == RC_OK && first < n_views; first += kMaxViews) {
         ViewSet S;

@@ -251,11 +251,10 @@ def test_render_views_equals_single_renders(seed, dtype, op, shading, n_views, s
                                               (np.uint16, "none", "central"),
                                               (np.uint8, "blinn_phong", "sobel3d")])
 def test_backward_views_equals_sum_of_single_views(dtype, shading, op):
-    """18 views: two reverse launches of at most 16 views each, against one
-    rc_render_backward per view.  Unshaded with a 256-entry table takes the
-    per-ray kernel; the 4096-entry table of u16 volumes and a shading model
-    take the chunked kernel, whose tile counter is zeroed before each
-    launch."""
+    """18 views: two reverse launches of at most 16 views each (the tile
+    counter zeroed before each), against one rc_render_backward per view:
+    unshaded with a 256-entry table (its LDS copy) and with the 4096-entry
+    table of u16 volumes (read from memory), and shaded."""
     sc, cams = _views_scene(18, dtype=dtype, shading=shading, op=op)
     vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
     tf = to_dev(sc.tf)
