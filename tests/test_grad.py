@@ -275,6 +275,34 @@ def test_backward_views_equals_sum_of_single_views(dtype, shading, op):
     assert _ok(a, b, c, d, "views vs single")
 
 
+def test_backward_views_of_mixed_sizes():
+    """Five shaded views of different image sizes (tile counts 1 .. 30, ragged
+    edges) in one reverse launch: the tiles of all views come from one counter
+    and map back to their view; equal to one rc_render_backward per view."""
+    sc = W.config_small(seed=67, dims=(26, 22, 19), dtype=np.uint16, image=(40, 36),
+                        op="zucker_hummel", shading="blinn_phong", ert=0.9, skip=True)
+    sizes = [(8, 8), (41, 37), (17, 50), (64, 24), (3, 5)]
+    cams = [W.orbit_camera((26, 22, 19), sc.spacing, 23.0 * i + 5.0, 20.0 - 6 * i, w, h)
+            for i, (w, h) in enumerate(sizes)]
+    vol = rc.rc_create_volume(to_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
+    rc.rc_build_bricks(vol, 8)
+    tf = to_dev(sc.tf)
+    auxes = [rc.new_aux(c) for c in cams]
+    rc.rc_render_views(vol, cams, tf, sc.shading, sc.options, auxes=auxes)
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    grads = [torch.randn((c["height"], c["width"], 4), device="cuda", generator=gen) for c in cams]
+    gv, gt = rc.rc_render_backward_views(vol, cams, tf, sc.shading, sc.options, auxes, grads)
+    gv1 = torch.zeros_like(gv)
+    gt1 = torch.zeros_like(gt)
+    for c, a, g in zip(cams, auxes, grads):
+        rc.rc_render_backward(vol, c, tf, sc.shading, sc.options, a, g, gv1, gt1)
+    torch.cuda.synchronize()
+    a, b = gv.cpu().numpy().astype(np.float64), gv1.cpu().numpy().astype(np.float64)
+    c, d = gt.cpu().numpy().astype(np.float64), gt1.cpu().numpy().astype(np.float64)
+    assert np.abs(b).max() > 0 and np.abs(d).max() > 0
+    assert _ok(a, b, c, d, "mixed sizes")
+
+
 def test_render_views_fn_matches_oracle():
     """Two views through the multi-view autograd function vs the FP64 adjoint."""
     sc, cams = _views_scene(2, seed=63)
