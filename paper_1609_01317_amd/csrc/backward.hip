@@ -453,11 +453,11 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
     const int wave_bytes = Bp.box_bytes;
     int zero_end = wave_bytes;
     // Resident waves take the tiles in that work order from a counter, one
-    // atomic add per tile: a wave whose rays end early takes
-    // the next tile instead of holding its slot until the block's slowest
-    // ray ends, and the block's table gradient is flushed once.  The
-    // counter only grows, so each wave leaves at its first index past the
-    // tiles (compared unsigned: a bad start also ends the loop).
+    // atomic add per tile: a wave whose rays end early takes the next tile
+    // instead of holding its slot until the block's slowest ray ends, and
+    // the block's table gradient is flushed once.  The counter only grows,
+    // so each wave leaves at its first index past the tiles (compared
+    // unsigned: a bad start also ends the loop).
     const unsigned n_units = (unsigned)S.block_off[S.n];
     for (;;) {
         int fetched = 0;
