@@ -61,11 +61,12 @@ def test_adjoint_matches_oracle_small(seed, dtype, ert, nearest, ref):
     assert _ok(gv, dv, gt, dt, f"seed {seed}")
 
 
-@pytest.mark.parametrize("tf_len", [1024, 1025, 2048, 2049])
+@pytest.mark.parametrize("tf_len", [1024, 1025, 4096, 4097])
 def test_adjoint_table_sizes(tf_len):
     """Table lengths on both sides of the two shared-memory limits of the
     adjoint kernel: the table is read from an LDS copy up to 1024 entries and
-    its gradient summed in LDS up to 2048, in global memory beyond."""
+    its gradient summed in LDS (shared by a block's waves) up to 4096, in
+    global memory beyond."""
     sc = W.config_small(seed=38, dims=(23, 19, 17), dtype=np.float32, image=(35, 27),
                         shading="none")
     tf = W.tf_ramps(tf_len, seed=38, alpha_max=0.3)
