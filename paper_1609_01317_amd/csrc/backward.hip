@@ -414,6 +414,22 @@ __device__ __forceinline__ void dv_box_flush(const RenderParams& P, const Backwa
     }
 }
 
+// Issue priority of a wave for its current tile, from the tile's longest ray
+// (last composited index, as a share of the most lattice steps a ray
+// through the volume can take): the long rays are serial chains that set
+// the pass's length, so the SIMD's arbiter serves their waves first and
+// the other waves fill the remaining issue slots.  Scheduling only.
+__device__ __forceinline__ void prioritise_long_rays(const RenderParams& P, int wave_last) {
+    const float dx = (float)(P.nx - 1) * P.s[0], dy = (float)(P.ny - 1) * P.s[1],
+                dz = (float)(P.nz - 1) * P.s[2];
+    const float kmax = sqrtf(dx * dx + dy * dy + dz * dz) * (float)P.inv_step + 2.0f;
+    const float r = (float)(wave_last + 1) / kmax;
+    if (r >= 0.75f) __builtin_amdgcn_s_setprio(3);
+    else if (r >= 0.5f) __builtin_amdgcn_s_setprio(2);
+    else if (r >= 0.25f) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 // The reverse march in chunks shared by the wave.  A wave renders one 8x8
 // pixel tile at a time; each lane runs its own ray back to front, and the
 // wave only agrees on a window of ray parameter (thi - len step, thi],
@@ -487,6 +503,7 @@ __global__ __launch_bounds__(64 * kBwdBoxWaves) void raycast_bwd_box(RenderParam
         }
         const int last = ax.k_last;
         const bool has = valid && R.K >= 0 && last >= 0 && last <= R.K;
+        prioritise_long_rays(P, wave_max(has ? last : -1));
         // Anchor: the last index a whose front transmittance T_a is at least
         // kTinyT.  Normally a = last + 1 with T_a = t_final; if the ray went
         // (nearly) opaque, a forward pass finds a instead.  Samples from a on
