@@ -32,22 +32,26 @@ rc_status hip_fail(hipError_t e, const char* what) {
 }
 
 // ---------------------------------------------------------------- kernels
-// One workgroup per run of kTileRun bricks along x: the run's voxels (64
-// rows of kBrick * kTileRun voxels, contiguous along x in the source) are read row
-// by row at clamped coordinates, so the padding replicates the edge
-// (Section 2.1: the grid is a 3D array of samples), staged in LDS, and
+// One workgroup per run of kTileRun bricks along x: the run's voxels (rows
+// of up to kBrick * kTileRun voxels, contiguous along x in the source) are
+// read row by row at clamped coordinates, so the padding replicates the
+// edge (Section 2.1: the grid is a 3D array of samples), staged in LDS, and
 // written out brick by brick in Morton order: the run's bricks are
 // consecutive in the bricked array, so both the reads and the writes are
-// contiguous runs.  The staging rows are padded (kRunRow, kRunPlane) so the
-// 64 voxels a wave reads back in Morton order fall in distinct LDS banks.
+// contiguous runs.  With `range` set the block also takes the one-voxel
+// high apron (one more row, plane and column) and writes each brick's value
+// range from LDS, as brick_minmax defines it.  The staging rows and planes
+// are padded (kRunRow, kRunPlane) so the 64 voxels a wave reads back in
+// Morton order fall in distinct LDS banks.
 constexpr int kTileRun = 8;
 constexpr int kRunRow = kBrick * kTileRun + 4;
-constexpr int kRunPlane = kBrick * kRunRow + 16;
+constexpr int kRunPlane = (kBrick + 1) * kRunRow + 12;
 template <typename T>
 __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* __restrict__ dst,
-                                                  int nx, int ny, int nz, int nbx, int nby,
-                                                  long long n_runs) {
-    __shared__ T run[kBrick * kRunPlane];      // voxel (x, y, z) of the run at z, y, x strides
+                                                  float2* __restrict__ range, int nx, int ny,
+                                                  int nz, int nbx, int nby, long long n_runs) {
+    // voxel (x, y, z) of the run (apron included) at z, y, x strides
+    __shared__ T run[(kBrick + 1) * kRunPlane];
     const long long r = blockIdx.x;
     if (r >= n_runs) return;
     const int runs_x = (nbx + kTileRun - 1) / kTileRun;
@@ -56,12 +60,14 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
     const int by = (int)(rest % nby), bz = (int)(rest / nby);
     const int bx0 = rx * kTileRun, nb = min(kTileRun, nbx - bx0);
     const int x0 = bx0 * kBrick, y0 = by * kBrick, z0 = bz * kBrick;
-    for (int i = threadIdx.x; i < kBrick * kBrick * kBrick * kTileRun; i += blockDim.x) {
-        const int xl = i % (kBrick * kTileRun), row = i / (kBrick * kTileRun);
-        if (xl >= kBrick * nb) continue;
-        const int x = min(x0 + xl, nx - 1), y = min(y0 + (row & 7), ny - 1),
-                  z = min(z0 + (row >> 3), nz - 1);
-        run[(row >> 3) * kRunPlane + (row & 7) * kRunRow + xl] = src[((long long)z * ny + y) * nx + x];
+    const int apron = range ? 1 : 0;
+    const int ncol = kBrick * nb + apron, nyr = kBrick + apron, nrow = nyr * (kBrick + apron);
+    for (int i = threadIdx.x; i < nrow * (kBrick * kTileRun + 1); i += blockDim.x) {
+        const int xl = i % (kBrick * kTileRun + 1), row = i / (kBrick * kTileRun + 1);
+        if (xl >= ncol) continue;
+        const int yl = row % nyr, zl = row / nyr;
+        const int x = min(x0 + xl, nx - 1), y = min(y0 + yl, ny - 1), z = min(z0 + zl, nz - 1);
+        run[zl * kRunPlane + yl * kRunRow + xl] = src[((long long)z * ny + y) * nx + x];
     }
     __syncthreads();
     T* out = dst + (((long long)bz * nby + by) * nbx + bx0) * kBrickVox;
@@ -69,6 +75,23 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
         const uint32_t m = (uint32_t)(i & (kBrickVox - 1));
         out[i] = run[(int)compact3(m >> 2) * kRunPlane + (int)compact3(m >> 1) * kRunRow +
                      (i / kBrickVox) * kBrick + (int)compact3(m)];
+    }
+    if (!range) return;
+    // one wave per brick of the run: min and max over its 9^3 voxels
+    const int lane = threadIdx.x & 63;
+    for (int j = threadIdx.x >> 6; j < nb; j += blockDim.x >> 6) {
+        float lo = INFINITY, hi = -INFINITY;
+        for (int q = lane; q < 729; q += 64) {
+            const int dx = q % 9, dy = (q / 9) % 9, dz = q / 81;
+            const float v = (float)run[dz * kRunPlane + dy * kRunRow + j * kBrick + dx];
+            lo = fminf(lo, v);
+            hi = fmaxf(hi, v);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = fminf(lo, __shfl_xor(lo, o));
+            hi = fmaxf(hi, __shfl_xor(hi, o));
+        }
+        if (lane == 0) range[((long long)bz * nby + by) * nbx + bx0 + j] = make_float2(lo, hi);
     }
 }
 
@@ -104,23 +127,24 @@ __global__ __launch_bounds__(64) void brick_minmax(const T* __restrict__ vox, fl
 
 static int elem_size(rc_dtype dt) { return dt == RC_U8 ? 1 : dt == RC_U16 ? 2 : 4; }
 
-static rc_status launch_tile(rc_volume* v, const void* src, hipStream_t st) {
+// range: the brick ranges to rebuild in the same pass, or null
+static rc_status launch_tile(rc_volume* v, const void* src, float2* range, hipStream_t st) {
     const long long total = (long long)((v->nbx + kTileRun - 1) / kTileRun) * v->nby * v->nbz;
     const unsigned grid = (unsigned)total;
     switch (v->dtype) {
         case RC_U8:
             hipLaunchKernelGGL(brick_tile<uint8_t>, dim3(grid), dim3(256), 0, st,
-                               (const uint8_t*)src, (uint8_t*)v->bricked, v->nx, v->ny, v->nz,
-                               v->nbx, v->nby, total);
+                               (const uint8_t*)src, (uint8_t*)v->bricked, range, v->nx, v->ny,
+                               v->nz, v->nbx, v->nby, total);
             break;
         case RC_U16:
             hipLaunchKernelGGL(brick_tile<uint16_t>, dim3(grid), dim3(256), 0, st,
-                               (const uint16_t*)src, (uint16_t*)v->bricked, v->nx, v->ny, v->nz,
-                               v->nbx, v->nby, total);
+                               (const uint16_t*)src, (uint16_t*)v->bricked, range, v->nx, v->ny,
+                               v->nz, v->nbx, v->nby, total);
             break;
         default:
             hipLaunchKernelGGL(brick_tile<float>, dim3(grid), dim3(256), 0, st,
-                               (const float*)src, (float*)v->bricked, v->nx, v->ny, v->nz,
+                               (const float*)src, (float*)v->bricked, range, v->nx, v->ny, v->nz,
                                v->nbx, v->nby, total);
     }
     RC_HIP(hipGetLastError());
@@ -194,7 +218,7 @@ extern "C" rc_status rc_create_volume(const void* src_dev, int nx, int ny, int n
     if (e != hipSuccess) { delete v; return hip_fail(e, "hipGetDevice"); }
     e = hipMalloc(&v->bricked, (size_t)nbricks * kBrickVox * v->elem_bytes);
     if (e != hipSuccess) { delete v; return hip_fail(e, "hipMalloc(bricked volume)"); }
-    rc_status st = launch_tile(v, src_dev, (hipStream_t)stream);
+    rc_status st = launch_tile(v, src_dev, nullptr, (hipStream_t)stream);
     if (st != RC_OK) { (void)hipFree(v->bricked); delete v; return st; }
     *out = v;
     return RC_OK;
@@ -203,10 +227,8 @@ extern "C" rc_status rc_create_volume(const void* src_dev, int nx, int ny, int n
 extern "C" rc_status rc_update_volume(rc_volume* v, const void* src_dev, void* stream) {
     if (!v) return fail(RC_E_INVALID, "rc_update_volume: volume is NULL");
     if (!src_dev) return fail(RC_E_INVALID, "rc_update_volume: src_dev is NULL");
-    rc_status st = launch_tile(v, src_dev, (hipStream_t)stream);
-    if (st != RC_OK) return st;
-    if (v->brick_range) return launch_minmax(v, (hipStream_t)stream);
-    return RC_OK;
+    // existing brick ranges are rebuilt from the same staged voxels
+    return launch_tile(v, src_dev, v->brick_range, (hipStream_t)stream);
 }
 
 extern "C" rc_status rc_build_bricks(rc_volume* v, int brick_edge, void* stream) {

@@ -88,6 +88,30 @@ def test_clip_box_and_anisotropic_spacing():
     _check(sc, options=opt)
 
 
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+def test_update_volume_rebuilds_brick_ranges(dtype):
+    """rc_update_volume on a handle whose brick ranges exist rebuilds them in
+    the ingest pass (the staged run of bricks plus its one-voxel apron): renders
+    with skipping from the updated handle equal, bit for bit and in their skip
+    counters, those of a fresh handle built from the same voxels.  Ragged
+    dimensions, so runs of fewer than 8 bricks and clamped aprons occur."""
+    sc = W.config_small(seed=71, dims=(77, 37, 29), dtype=dtype, image=(48, 40), op="sobel3d",
+                        ert=0.95, skip=True)
+    old = np.ascontiguousarray(np.roll(sc.volume, (5, -7, 11), axis=(0, 1, 2)))
+    upd = rc.rc_create_volume(to_dev(old), sc.spacing, sc.vmin, sc.vmax)
+    rc.rc_build_bricks(upd, 8)
+    rc.rc_update_volume(upd, to_dev(sc.volume))
+    fresh = gpu_volume(sc, bricks=True)
+    cams = [W.orbit_camera((77, 37, 29), sc.spacing, 40.0 * i, 25.0 - 10 * i, 48, 40)
+            for i in range(3)]
+    for cam in cams:
+        a = gpu_render(sc, cam=cam, vol=upd, stats=True)
+        b = gpu_render(sc, cam=cam, vol=fresh, stats=True)
+        assert np.array_equal(a["rgba"], b["rgba"]) and np.array_equal(a["k_last"], b["k_last"])
+        np.testing.assert_array_equal(a["stats"], b["stats"])
+        assert b["stats"][5] > 0            # some chunks were skipped as empty
+
+
 def test_skip_is_lossless_bitwise():
     """Skipped samples have alpha exactly 0, so skip on == skip off bit for bit."""
     sc = W.config_small(seed=13, dims=(40, 36, 33), dtype=np.uint16, image=(48, 40),
