@@ -5,7 +5,7 @@
 #include <new>
 #include <string>
 
-#include "rc_internal.h"
+#include "march.h"      // RC_IDX: index checks of the bounds-checked build
 
 namespace rc {
 
@@ -49,7 +49,8 @@ constexpr int kRunPlane = (kBrick + 1) * kRunRow + 12;
 template <typename T>
 __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* __restrict__ dst,
                                                   float2* __restrict__ range, int nx, int ny,
-                                                  int nz, int nbx, int nby, long long n_runs) {
+                                                  int nz, int nbx, int nby, long long n_runs,
+                                                  unsigned int* dbg) {
     // voxel (x, y, z) of the run (apron included) at z, y, x strides
     __shared__ T run[(kBrick + 1) * kRunPlane];
     const long long r = blockIdx.x;
@@ -60,6 +61,9 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
     const int by = (int)(rest % nby), bz = (int)(rest / nby);
     const int bx0 = rx * kTileRun, nb = min(kTileRun, nbx - bx0);
     const int x0 = bx0 * kBrick, y0 = by * kBrick, z0 = bz * kBrick;
+    const long long n_src = (long long)nx * ny * nz;
+    const long long n_bricks = (long long)nbx * nby * ((nz + kBrick - 1) / kBrick);
+    constexpr int n_lds = (kBrick + 1) * kRunPlane;
     const int apron = range ? 1 : 0;
     const int ncol = kBrick * nb + apron, nyr = kBrick + apron, nrow = nyr * (kBrick + apron);
     for (int i = threadIdx.x; i < nrow * (kBrick * kTileRun + 1); i += blockDim.x) {
@@ -67,14 +71,17 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
         if (xl >= ncol) continue;
         const int yl = row % nyr, zl = row / nyr;
         const int x = min(x0 + xl, nx - 1), y = min(y0 + yl, ny - 1), z = min(z0 + zl, nz - 1);
-        run[zl * kRunPlane + yl * kRunRow + xl] = src[((long long)z * ny + y) * nx + x];
+        run[RC_IDX(dbg, zl * kRunPlane + yl * kRunRow + xl, n_lds)] =
+            src[RC_IDX(dbg, ((long long)z * ny + y) * nx + x, n_src)];
     }
     __syncthreads();
-    T* out = dst + (((long long)bz * nby + by) * nbx + bx0) * kBrickVox;
+    const long long first = (((long long)bz * nby + by) * nbx + bx0) * kBrickVox;
     for (int i = threadIdx.x; i < kBrickVox * nb; i += blockDim.x) {
         const uint32_t m = (uint32_t)(i & (kBrickVox - 1));
-        out[i] = run[(int)compact3(m >> 2) * kRunPlane + (int)compact3(m >> 1) * kRunRow +
-                     (i / kBrickVox) * kBrick + (int)compact3(m)];
+        dst[RC_IDX(dbg, first + i, n_bricks * kBrickVox)] =
+            run[RC_IDX(dbg, (int)compact3(m >> 2) * kRunPlane + (int)compact3(m >> 1) * kRunRow +
+                                (i / kBrickVox) * kBrick + (int)compact3(m),
+                        n_lds)];
     }
     if (!range) return;
     // one wave per brick of the run: min and max over its 9^3 voxels
@@ -83,7 +90,8 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
         float lo = INFINITY, hi = -INFINITY;
         for (int q = lane; q < 729; q += 64) {
             const int dx = q % 9, dy = (q / 9) % 9, dz = q / 81;
-            const float v = (float)run[dz * kRunPlane + dy * kRunRow + j * kBrick + dx];
+            const float v =
+                (float)run[RC_IDX(dbg, dz * kRunPlane + dy * kRunRow + j * kBrick + dx, n_lds)];
             lo = fminf(lo, v);
             hi = fmaxf(hi, v);
         }
@@ -91,7 +99,9 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
             lo = fminf(lo, __shfl_xor(lo, o));
             hi = fmaxf(hi, __shfl_xor(hi, o));
         }
-        if (lane == 0) range[((long long)bz * nby + by) * nbx + bx0 + j] = make_float2(lo, hi);
+        if (lane == 0)
+            range[RC_IDX(dbg, ((long long)bz * nby + by) * nbx + bx0 + j, n_bricks)] =
+                make_float2(lo, hi);
     }
 }
 
@@ -101,7 +111,8 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
 template <typename T>
 __global__ __launch_bounds__(64) void brick_minmax(const T* __restrict__ vox, float2* __restrict__ out,
                                                    int nx, int ny, int nz, int nbx, int nby,
-                                                   int sy, int sz, long long nbricks) {
+                                                   int sy, int sz, long long nbricks,
+                                                   unsigned int* dbg) {
     long long b = blockIdx.x;
     if (b >= nbricks) return;
     int bx = (int)(b % nbx);
@@ -114,7 +125,8 @@ __global__ __launch_bounds__(64) void brick_minmax(const T* __restrict__ vox, fl
         int x = min(bx * kBrick + dx, nx - 1);
         int y = min(by * kBrick + dy, ny - 1);
         int z = min(bz * kBrick + dz, nz - 1);
-        float v = (float)vox[off_x(x) + off_y(y, sy) + off_z(z, sz)];
+        float v = (float)vox[RC_IDX(dbg, off_x(x) + off_y(y, sy) + off_z(z, sz),
+                                    nbricks * kBrickVox)];
         lo = fminf(lo, v);
         hi = fmaxf(hi, v);
     }
@@ -122,7 +134,7 @@ __global__ __launch_bounds__(64) void brick_minmax(const T* __restrict__ vox, fl
         lo = fminf(lo, __shfl_xor(lo, o));
         hi = fmaxf(hi, __shfl_xor(hi, o));
     }
-    if (threadIdx.x == 0) out[b] = make_float2(lo, hi);
+    if (threadIdx.x == 0) out[RC_IDX(dbg, b, nbricks)] = make_float2(lo, hi);
 }
 
 static int elem_size(rc_dtype dt) { return dt == RC_U8 ? 1 : dt == RC_U16 ? 2 : 4; }
@@ -135,17 +147,17 @@ static rc_status launch_tile(rc_volume* v, const void* src, float2* range, hipSt
         case RC_U8:
             hipLaunchKernelGGL(brick_tile<uint8_t>, dim3(grid), dim3(256), 0, st,
                                (const uint8_t*)src, (uint8_t*)v->bricked, range, v->nx, v->ny,
-                               v->nz, v->nbx, v->nby, total);
+                               v->nz, v->nbx, v->nby, total, debug_counter());
             break;
         case RC_U16:
             hipLaunchKernelGGL(brick_tile<uint16_t>, dim3(grid), dim3(256), 0, st,
                                (const uint16_t*)src, (uint16_t*)v->bricked, range, v->nx, v->ny,
-                               v->nz, v->nbx, v->nby, total);
+                               v->nz, v->nbx, v->nby, total, debug_counter());
             break;
         default:
             hipLaunchKernelGGL(brick_tile<float>, dim3(grid), dim3(256), 0, st,
                                (const float*)src, (float*)v->bricked, range, v->nx, v->ny, v->nz,
-                               v->nbx, v->nby, total);
+                               v->nbx, v->nby, total, debug_counter());
     }
     RC_HIP(hipGetLastError());
     return RC_OK;
@@ -158,17 +170,17 @@ static rc_status launch_minmax(rc_volume* v, hipStream_t st) {
         case RC_U8:
             hipLaunchKernelGGL(brick_minmax<uint8_t>, grid, block, 0, st,
                                (const uint8_t*)v->bricked, v->brick_range, v->nx, v->ny, v->nz,
-                               v->nbx, v->nby, sy, sz, v->nbricks);
+                               v->nbx, v->nby, sy, sz, v->nbricks, debug_counter());
             break;
         case RC_U16:
             hipLaunchKernelGGL(brick_minmax<uint16_t>, grid, block, 0, st,
                                (const uint16_t*)v->bricked, v->brick_range, v->nx, v->ny, v->nz,
-                               v->nbx, v->nby, sy, sz, v->nbricks);
+                               v->nbx, v->nby, sy, sz, v->nbricks, debug_counter());
             break;
         default:
             hipLaunchKernelGGL(brick_minmax<float>, grid, block, 0, st, (const float*)v->bricked,
                                v->brick_range, v->nx, v->ny, v->nz, v->nbx, v->nby, sy, sz,
-                               v->nbricks);
+                               v->nbricks, debug_counter());
     }
     RC_HIP(hipGetLastError());
     return RC_OK;

@@ -59,6 +59,8 @@ def run_cases():
         sc = W.config_small(**c)
         vol = rc.rc_create_volume(_dev(sc.volume), sc.spacing, sc.vmin, sc.vmax)
         rc.rc_build_bricks(vol, 8)
+        # re-ingest: the brick ranges are rebuilt in the ingest pass
+        rc.rc_update_volume(vol, _dev(sc.volume))
         tf = _dev(sc.tf)
         cam = sc.cameras[0]
         variants = [("plain", {}), ("nearest", {"nearest": True}),
