@@ -44,6 +44,14 @@ rc_status hip_fail(hipError_t e, const char* what) {
 // are padded (kRunRow, kRunPlane) so the 64 voxels a wave reads back in
 // Morton order fall in distinct LDS banks.
 constexpr int kTileRun = 8;
+// 8 voxels of a Morton group, stored with one (16-byte for u16) vector write
+template <typename T> struct alignas(8 * sizeof(T)) Group {
+    T v[8];
+};
+// 4 consecutive voxels of a source row, read with one vector load
+template <typename T> struct alignas(4 * sizeof(T)) Quad {
+    T v[4];
+};
 constexpr int kRunRow = kBrick * kTileRun + 4;
 constexpr int kRunPlane = (kBrick + 1) * kRunRow + 12;
 template <typename T>
@@ -52,7 +60,7 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
                                                   int nz, int nbx, int nby, long long n_runs,
                                                   unsigned int* dbg) {
     // voxel (x, y, z) of the run (apron included) at z, y, x strides
-    __shared__ T run[(kBrick + 1) * kRunPlane];
+    __shared__ __align__(16) T run[(kBrick + 1) * kRunPlane];
     const long long r = blockIdx.x;
     if (r >= n_runs) return;
     const int runs_x = (nbx + kTileRun - 1) / kTileRun;
@@ -66,22 +74,44 @@ __global__ __launch_bounds__(256) void brick_tile(const T* __restrict__ src, T* 
     constexpr int n_lds = (kBrick + 1) * kRunPlane;
     const int apron = range ? 1 : 0;
     const int ncol = kBrick * nb + apron, nyr = kBrick + apron, nrow = nyr * (kBrick + apron);
-    for (int i = threadIdx.x; i < nrow * (kBrick * kTileRun + 1); i += blockDim.x) {
-        const int xl = i % (kBrick * kTileRun + 1), row = i / (kBrick * kTileRun + 1);
-        if (xl >= ncol) continue;
+    // Rows whose voxels sit 4-aligned in the source (an aligned base, nx a
+    // multiple of 4; x0 is a multiple of 64) are read 4 voxels per load where
+    // all 4 lie inside the row; the rest, and other sources, voxel by voxel.
+    constexpr int kQuads = kBrick * kTileRun / 4 + 1;       // 16 quads + the apron column
+    const bool quads = (nx & 3) == 0 && ((uintptr_t)src & (4 * sizeof(T) - 1)) == 0;
+    const int per_row = quads ? kQuads : kBrick * kTileRun + 1;
+    for (int i = threadIdx.x; i < nrow * per_row; i += blockDim.x) {
+        const int c = i % per_row, row = i / per_row;
         const int yl = row % nyr, zl = row / nyr;
-        const int x = min(x0 + xl, nx - 1), y = min(y0 + yl, ny - 1), z = min(z0 + zl, nz - 1);
-        run[RC_IDX(dbg, zl * kRunPlane + yl * kRunRow + xl, n_lds)] =
-            src[RC_IDX(dbg, ((long long)z * ny + y) * nx + x, n_src)];
+        const int y = min(y0 + yl, ny - 1), z = min(z0 + zl, nz - 1);
+        const long long line = ((long long)z * ny + y) * nx;
+        const int l = zl * kRunPlane + yl * kRunRow;
+        const int xl = quads ? min(4 * c, kBrick * kTileRun) : c;
+        if (xl >= ncol) continue;
+        if (quads && c < kQuads - 1 && x0 + xl + 3 < nx) {
+            *(Quad<T>*)&run[RC_IDX(dbg, l + xl, n_lds - 3)] =
+                *(const Quad<T>*)&src[RC_IDX(dbg, line + x0 + xl, n_src - 3)];
+        } else {
+            const int n = (quads && c < kQuads - 1) ? 4 : 1;
+            for (int d = 0; d < n; ++d)
+                run[RC_IDX(dbg, l + xl + d, n_lds)] =
+                    src[RC_IDX(dbg, line + min(x0 + xl + d, nx - 1), n_src)];
+        }
     }
     __syncthreads();
+    // one 2x2x2 Morton group (8 consecutive voxels of the bricked array) per
+    // thread and step, written with one vector store
     const long long first = (((long long)bz * nby + by) * nbx + bx0) * kBrickVox;
-    for (int i = threadIdx.x; i < kBrickVox * nb; i += blockDim.x) {
-        const uint32_t m = (uint32_t)(i & (kBrickVox - 1));
-        dst[RC_IDX(dbg, first + i, n_bricks * kBrickVox)] =
-            run[RC_IDX(dbg, (int)compact3(m >> 2) * kRunPlane + (int)compact3(m >> 1) * kRunRow +
-                                (i / kBrickVox) * kBrick + (int)compact3(m),
-                        n_lds)];
+    for (int grp = threadIdx.x; grp < (kBrickVox / 8) * nb; grp += blockDim.x) {
+        const uint32_t m = (uint32_t)(grp & (kBrickVox / 8 - 1)) << 3;
+        const int l0 = (int)compact3(m >> 2) * kRunPlane + (int)compact3(m >> 1) * kRunRow +
+                       (grp / (kBrickVox / 8)) * kBrick + (int)compact3(m);
+        Group<T> g;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            g.v[q] = run[RC_IDX(dbg, l0 + (q >> 2) * kRunPlane + ((q >> 1) & 1) * kRunRow + (q & 1),
+                                n_lds)];
+        *(Group<T>*)(dst + RC_IDX(dbg, first + 8ll * grp, n_bricks * kBrickVox - 7)) = g;
     }
     if (!range) return;
     // one wave per brick of the run: min and max over its 9^3 voxels

@@ -88,22 +88,24 @@ def test_clip_box_and_anisotropic_spacing():
     _check(sc, options=opt)
 
 
-@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
-def test_update_volume_rebuilds_brick_ranges(dtype):
+@pytest.mark.parametrize("dtype,dims", [(np.uint8, (77, 37, 29)), (np.uint16, (77, 37, 29)),
+                                        (np.float32, (77, 37, 29)), (np.uint16, (68, 30, 21)),
+                                        (np.uint8, (132, 12, 9))])
+def test_update_volume_rebuilds_brick_ranges(dtype, dims):
     """rc_update_volume on a handle whose brick ranges exist rebuilds them in
     the ingest pass (the staged run of bricks plus its one-voxel apron): renders
     with skipping from the updated handle equal, bit for bit and in their skip
     counters, those of a fresh handle built from the same voxels.  Ragged
-    dimensions, so runs of fewer than 8 bricks and clamped aprons occur."""
-    sc = W.config_small(seed=71, dims=(77, 37, 29), dtype=dtype, image=(48, 40), op="sobel3d",
+    dimensions, so runs of fewer than 8 bricks and clamped aprons occur;
+    rows of a multiple of 4 voxels take the 4-voxel loads."""
+    sc = W.config_small(seed=71, dims=dims, dtype=dtype, image=(48, 40), op="sobel3d",
                         ert=0.95, skip=True)
     old = np.ascontiguousarray(np.roll(sc.volume, (5, -7, 11), axis=(0, 1, 2)))
     upd = rc.rc_create_volume(to_dev(old), sc.spacing, sc.vmin, sc.vmax)
     rc.rc_build_bricks(upd, 8)
     rc.rc_update_volume(upd, to_dev(sc.volume))
     fresh = gpu_volume(sc, bricks=True)
-    cams = [W.orbit_camera((77, 37, 29), sc.spacing, 40.0 * i, 25.0 - 10 * i, 48, 40)
-            for i in range(3)]
+    cams = [W.orbit_camera(dims, sc.spacing, 40.0 * i, 25.0 - 10 * i, 48, 40) for i in range(3)]
     for cam in cams:
         a = gpu_render(sc, cam=cam, vol=upd, stats=True)
         b = gpu_render(sc, cam=cam, vol=fresh, stats=True)
