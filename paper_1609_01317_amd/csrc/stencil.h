@@ -49,65 +49,6 @@ __device__ __forceinline__ WT centre(WT s, WT d) {
     else return fmaf(OpTaps<OP>::gamma, d, s);
 }
 
-// What one z plane contributes to S at a voxel of the plane below, on or
-// above it: v[b][a] = V(x + a - 1, y + b - 1) on that plane.
-template <typename WT> struct PlaneP {
-    WT ax, ay;          // sum_b A_b dx(b), sum_a A_a dy(a)
-    WT dx0, dy0;        // the centre row / column differences
-};
-
-template <typename VT, int OP>
-__device__ __forceinline__ PlaneP<typename StencilT<VT, OP>::WT> plane_partials(
-    const typename StencilT<VT, OP>::DT v[3][3]) {
-    using WT = typename StencilT<VT, OP>::WT;
-    PlaneP<WT> r;
-    r.dx0 = (WT)(v[1][2] - v[1][0]);
-    r.dy0 = (WT)(v[2][1] - v[0][1]);
-    if constexpr (OpTaps<OP>::kSep) {
-        r.ax = sm3<OP, WT>((WT)(v[0][2] - v[0][0]), r.dx0, (WT)(v[2][2] - v[2][0]));
-        r.ay = sm3<OP, WT>((WT)(v[2][0] - v[0][0]), r.dy0, (WT)(v[2][2] - v[0][2]));
-    } else {
-        r.ax = r.ay = (WT)0;
-    }
-    return r;
-}
-
-// S_z at a voxel from the planes below (lo) and above (hi) it.
-template <typename VT, int OP>
-__device__ __forceinline__ typename StencilT<VT, OP>::WT z_part(
-    const typename StencilT<VT, OP>::DT lo[3][3], const typename StencilT<VT, OP>::DT hi[3][3]) {
-    using WT = typename StencilT<VT, OP>::WT;
-    const WT d11 = (WT)(hi[1][1] - lo[1][1]);
-    if constexpr (!OpTaps<OP>::kSep) {
-        return d11;
-    } else {
-        WT r[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            r[b] = sm3<OP, WT>((WT)(hi[b][0] - lo[b][0]),
-                               b == 1 ? d11 : (WT)(hi[b][1] - lo[b][1]),
-                               (WT)(hi[b][2] - lo[b][2]));
-        return centre<OP, WT>(sm3<OP, WT>(r[0], r[1], r[2]), d11);
-    }
-}
-
-// S at a voxel from its three planes' partials and its z part.
-template <typename VT, int OP>
-__device__ __forceinline__ void voxel_stencil(const PlaneP<typename StencilT<VT, OP>::WT>& lo,
-                                              const PlaneP<typename StencilT<VT, OP>::WT>& mid,
-                                              const PlaneP<typename StencilT<VT, OP>::WT>& hi,
-                                              typename StencilT<VT, OP>::WT sz, float S[3]) {
-    using WT = typename StencilT<VT, OP>::WT;
-    if constexpr (OpTaps<OP>::kSep) {
-        S[0] = (float)centre<OP, WT>(sm3<OP, WT>(lo.ax, mid.ax, hi.ax), mid.dx0);
-        S[1] = (float)centre<OP, WT>(sm3<OP, WT>(lo.ay, mid.ay, hi.ay), mid.dy0);
-    } else {
-        S[0] = (float)mid.dx0;
-        S[1] = (float)mid.dy0;
-    }
-    S[2] = (float)sz;
-}
-
 // Gradient at the point of cell C from the 4x4x4 footprint of ox/oy/oz in
 // the bricked volume: the operator at each of the cell's 8 corners, then
 // their trilinear blend (x, then y, then z), scaled to normalised value per
@@ -134,39 +75,75 @@ __device__ __forceinline__ void gradient_exact(const RenderParams& P, const VT* 
                              : used ? (DT)base[ox[x] + oy[y] + oz[z]]
                                     : (DT)0;
             }
-    // plane partials of the 4 corner columns on the 4 planes
-    PlaneP<WT> pp[4][2][2];
+    // S at the 8 corners (i, j, k) = footprint voxel (i + 1, j + 1, k + 1),
+    // separably and differences first: the +-1 differences along each axis
+    // at the corner positions, then the smoothing along the other two axes,
+    // then the centre term.  S_x: x differences, smoothed along y, then z.
+    WT s3[3][2][2][2];              // [component][k][j][i]
+    if constexpr (OpTaps<OP>::kSep) {
+        WT dx[4][4][2], dy[4][2][4], dz[2][4][4];
 #pragma unroll
-    for (int z = 0; z < 4; ++z)
+        for (int z = 0; z < 4; ++z)
 #pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
+            for (int y = 0; y < 4; ++y)
 #pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                DT w[3][3];
+                for (int x = 0; x < 4; ++x) {
+                    if (x < 2) dx[z][y][x] = (WT)(f[z][y][x + 2] - f[z][y][x]);
+                    if (y < 2) dy[z][y][x] = (WT)(f[z][y + 2][x] - f[z][y][x]);
+                    if (z < 2) dz[z][y][x] = (WT)(f[z + 2][y][x] - f[z][y][x]);
+                }
+        WT tx[4][2][2], ty[4][2][2], tz[2][4][2];
 #pragma unroll
-                for (int b = 0; b < 3; ++b)
+        for (int z = 0; z < 4; ++z)
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) w[b][a] = f[z][cy + b][cx + a];
-                pp[z][cy][cx] = plane_partials<VT, OP>(w);
-            }
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    tx[z][j][i] = sm3<OP, WT>(dx[z][j][i], dx[z][j + 1][i], dx[z][j + 2][i]);
+                    ty[z][j][i] = sm3<OP, WT>(dy[z][j][i], dy[z][j][i + 1], dy[z][j][i + 2]);
+                }
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    tz[k][y][i] = sm3<OP, WT>(dz[k][y][i], dz[k][y][i + 1], dz[k][y][i + 2]);
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    s3[0][k][j][i] = centre<OP, WT>(
+                        sm3<OP, WT>(tx[k][j][i], tx[k + 1][j][i], tx[k + 2][j][i]),
+                        dx[k + 1][j + 1][i]);
+                    s3[1][k][j][i] = centre<OP, WT>(
+                        sm3<OP, WT>(ty[k][j][i], ty[k + 1][j][i], ty[k + 2][j][i]),
+                        dy[k + 1][j][i + 1]);
+                    s3[2][k][j][i] = centre<OP, WT>(
+                        sm3<OP, WT>(tz[k][j][i], tz[k][j + 1][i], tz[k][j + 2][i]),
+                        dz[k][j + 1][i + 1]);
+                }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    s3[0][k][j][i] = (WT)(f[k + 1][j + 1][i + 2] - f[k + 1][j + 1][i]);
+                    s3[1][k][j][i] = (WT)(f[k + 1][j + 2][i + 1] - f[k + 1][j][i + 1]);
+                    s3[2][k][j][i] = (WT)(f[k + 2][j + 1][i + 1] - f[k][j + 1][i + 1]);
+                }
+    }
     float sx[8], sy[8], sz[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const int cx = q & 1, cy = (q >> 1) & 1, cz = q >> 2;
-        DT lo[3][3], hi[3][3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lo[b][a] = f[cz][cy + b][cx + a];
-                hi[b][a] = f[cz + 2][cy + b][cx + a];
-            }
-        float S[3];
-        voxel_stencil<VT, OP>(pp[cz][cy][cx], pp[cz + 1][cy][cx], pp[cz + 2][cy][cx],
-                              z_part<VT, OP>(lo, hi), S);
-        sx[q] = S[0];
-        sy[q] = S[1];
-        sz[q] = S[2];
+        const int i = q & 1, j = (q >> 1) & 1, k = q >> 2;
+        sx[q] = (float)s3[0][k][j][i];
+        sy[q] = (float)s3[1][k][j][i];
+        sz[q] = (float)s3[2][k][j][i];
     }
     g[0] = trilinear(sx, C) * P.gscale[0];
     g[1] = trilinear(sy, C) * P.gscale[1];
